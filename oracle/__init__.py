@@ -1,0 +1,176 @@
+"""CPU oracle for the Navier-Stokes momentum RHS assembly -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and this
+package never imports the GPU library: the two share no code.
+
+``nsasm_oracle.c`` is a plain FP64 element loop (see its header for the weak
+form and the readings taken where the paper is silent); ``exact.py`` is an
+exact rational checker that pins it.  This module builds the C library with gcc
+and wraps it with ctypes/numpy.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "nsasm_oracle.c"), os.path.join(_HERE, "element_body.inc")]
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp, _SRC[0], "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    i64 = ctypes.c_int64
+    d = ctypes.c_double
+    lib.oracle_default_threads.restype = ctypes.c_int
+    lib.oracle_geometry.argtypes = [i64, dp, i64, ip, dp, dp]
+    lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, dp]
+    lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, dp, ctypes.c_int]
+    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, d, d, d, dp, dp, dp]
+    lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, dp, ctypes.c_int]
+    for fn in ("oracle_geometry", "oracle_eddy", "oracle_rhs", "oracle_rhs_complex", "oracle_vjp"):
+        getattr(lib, fn).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a, ctype=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+_ERRORS = {1: "node id out of range", 2: "degenerate element (det J == 0)", 3: "out of memory"}
+
+
+def _check(status):
+    if status != 0:
+        raise ValueError(f"oracle: {_ERRORS.get(status, status)}")
+
+
+class Params:
+    """Physical parameters: density, molecular viscosity, Smagorinsky constant
+    (0 = no eddy viscosity) and constant body-force acceleration."""
+
+    def __init__(self, rho=1.0, mu=1e-3, cs=0.0, f=(0.1, -0.2, 0.3)):
+        self.rho, self.mu, self.cs = float(rho), float(mu), float(cs)
+        self.f = np.asarray(f, dtype=np.float64).reshape(3).copy()
+
+    def args(self):
+        return (self.rho, self.mu, self.cs, _ptr(self.f))
+
+
+def default_threads() -> int:
+    return _load().oracle_default_threads()
+
+
+def geometry(coords, conn):
+    """(V_e, grad N) per element: shapes (Ne,), (Ne, 4, 3)."""
+    x, c = _f64(coords), _i32(conn)
+    ne = c.shape[0]
+    vol = np.empty(ne)
+    gn = np.empty((ne, 4, 3))
+    _check(_load().oracle_geometry(x.shape[0], _ptr(x), ne, _ptr(c, ctypes.c_int32), _ptr(vol), _ptr(gn)))
+    return vol, gn
+
+
+def eddy(coords, conn, u, prm: Params):
+    """Per-element eddy viscosity mu_t, shape (Ne,)."""
+    x, c, uu = _f64(coords), _i32(conn), _f64(u)
+    out = np.empty(c.shape[0])
+    _check(_load().oracle_eddy(x.shape[0], _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(uu),
+                               *prm.args(), _ptr(out)))
+    return out
+
+
+def rhs(coords, conn, u, p, prm: Params, nthreads: int = 0):
+    """Assembled RHS (Nn, 3)."""
+    x, c = _f64(coords), _i32(conn)
+    nn = x.shape[0]
+    uu, pp = _f64(u, (nn, 3)), _f64(p, (nn,))
+    out = np.empty((nn, 3))
+    _check(_load().oracle_rhs(nn, _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(uu), _ptr(pp),
+                              *prm.args(), _ptr(out), int(nthreads)))
+    return out
+
+
+def rhs_complex(coords, conn, u, p, prm: Params):
+    """RHS for a complex velocity field (complex-step differentiation)."""
+    x, c = _f64(coords), _i32(conn)
+    nn = x.shape[0]
+    u = np.asarray(u, dtype=np.complex128).reshape(nn, 3)
+    ur, ui = _f64(u.real), _f64(u.imag)
+    pp = _f64(p, (nn,))
+    rr, ri = np.empty((nn, 3)), np.empty((nn, 3))
+    _check(_load().oracle_rhs_complex(nn, _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(ur),
+                                      _ptr(ui), _ptr(pp), *prm.args(), _ptr(rr), _ptr(ri)))
+    return rr + 1j * ri
+
+
+def vjp(coords, conn, u, lam, prm: Params, nthreads: int = 0):
+    """Velocity VJP (dR/du)^T lam, shape (Nn, 3)."""
+    x, c = _f64(coords), _i32(conn)
+    nn = x.shape[0]
+    uu, ll = _f64(u, (nn, 3)), _f64(lam, (nn, 3))
+    out = np.empty((nn, 3))
+    _check(_load().oracle_vjp(nn, _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(uu), _ptr(ll),
+                              *prm.args(), _ptr(out), int(nthreads)))
+    return out
+
+
+def dense_jacobian_complex_step(coords, conn, u, p, prm: Params, h: float = 1e-30):
+    """dR/du as a dense (3 Nn, 3 Nn) matrix by complex-step differentiation
+    (Squire & Trapp 1998): column k = Im R(u + i h e_k) / h, free of
+    subtractive cancellation."""
+    nn = np.asarray(coords).shape[0]
+    u = _f64(u, (nn, 3))
+    jac = np.empty((3 * nn, 3 * nn))
+    for k in range(3 * nn):
+        du = np.zeros(3 * nn)
+        du[k] = h
+        r = rhs_complex(coords, conn, u + 1j * du.reshape(nn, 3), p, prm)
+        jac[:, k] = r.imag.reshape(-1) / h
+    return jac
+
+
+def rel_l2(a, b) -> float:
+    """||a - b||_2 / ||b||_2 (b is the reference)."""
+    a = np.asarray(a, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))

@@ -1,0 +1,371 @@
+/*
+ * nsasm CPU oracle -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * Plain, slow, FP64 implementation of the element-by-element assembly of the
+ * incompressible Navier-Stokes momentum right-hand side over linear tetrahedra
+ * (the RHS assembly of Sec. II, specialised to P1 tetrahedra with four Gauss
+ * points, constant density and viscosity and an eddy viscosity computed once per
+ * element as in Sec. IV-B).  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no source with the GPU library.
+ *
+ * The paper does not print the discrete equations (it defers them to the Alya
+ * formulation paper), so the weak form below is the standard Galerkin one; the
+ * readings taken where the paper is silent are:
+ *   convective term  advective form  -rho (u . grad) u
+ *   pressure term    gradient form   -grad p (no integration by parts)
+ *   viscous term     Laplacian form  -(mu + mu_t) grad N_a . grad u_i
+ *   eddy viscosity   Smagorinsky, Delta = V^(1/3), |S| = sqrt(2 S:S)
+ *   body force       +rho f, constant acceleration
+ *   orientation      V = |det J| / 6
+ *   no boundary conditions, no stabilisation, one time level.
+ *
+ * For element e with vertices a = 0..3:
+ *   J = [x1-x0 | x2-x0 | x3-x0], D = det J, V = |D|/6,
+ *   grad N_a = row a of J^-1 (a = 1..3), grad N_0 = -(grad N_1 + grad N_2 + grad N_3),
+ *   G = grad u, q = grad p, mu_e = mu + mu_t,
+ *   Gauss points g = 0..3: N_a(g) = alpha if a == g else beta, weight V/4,
+ *   u^g = sum_a N_a(g) u_a,  r^g = -rho G u^g - q + rho f,
+ *   R^e_a = sum_g (V/4) N_a(g) r^g - mu_e V G grad N_a,
+ *   R_n = sum over (e, a) with node(e, a) = n of R^e_a.
+ *
+ * Velocity vector-Jacobian product g = (dR/du)^T lambda (not in the paper; the
+ * adjoint form of the same assembly), per element with lambda^g, Lambda =
+ * grad lambda, Phi = Lambda : G:
+ *   g_b = -rho sum_g (V/4) [ N_b(g) G^T lambda^g + lambda^g (u^g . grad N_b) ]
+ *         - mu_e V Lambda grad N_b - V Phi d mu_t / d u_b,
+ *   d mu_t / d u_{b,k} = rho (cs Delta)^2 (2/|S|) sum_j S_kj d_j N_b  (0 if |S| = 0).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double rho, mu, cs;
+    double f[3];
+} oracle_params;
+
+/* Symmetric 4-point rule on the tetrahedron, exact for degree 2. */
+#define GAUSS_ALPHA ((5.0 + 3.0 * sqrt(5.0)) / 20.0)
+#define GAUSS_BETA ((5.0 - sqrt(5.0)) / 20.0)
+
+enum { ORACLE_OK = 0, ORACLE_BAD_INDEX = 1, ORACLE_DEGENERATE = 2, ORACLE_NOMEM = 3 };
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Jacobian of the map from the reference tetrahedron, its determinant, the
+ * volume and the constant shape-function gradients.  Returns 0 when D == 0. */
+static int element_geometry(const double xe[4][3], double gradN[4][3], double *vol, double *det) {
+    double J[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) J[i][c] = xe[c + 1][i] - xe[0][i]; /* column c = x_{c+1} - x_0 */
+    double D = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+             - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+             + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    *det = D;
+    if (D == 0.0 || !isfinite(D)) return 0;
+    /* inverse = adjugate / D; adj[r][c] = cofactor[c][r] */
+    double inv[3][3];
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / D;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / D;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / D;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / D;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / D;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / D;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / D;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / D;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / D;
+    for (int a = 1; a < 4; ++a)
+        for (int j = 0; j < 3; ++j) gradN[a][j] = inv[a - 1][j];
+    for (int j = 0; j < 3; ++j) gradN[0][j] = -(gradN[1][j] + gradN[2][j] + gradN[3][j]);
+    *vol = fabs(D) / 6.0;
+    return 1;
+}
+
+/* ------------------------------------------- real and complex element bodies */
+
+#define SCALAR double
+#define SQRT_S sqrt
+#define FN(name) name##_r
+#include "element_body.inc"
+#undef SCALAR
+#undef SQRT_S
+#undef FN
+
+#define SCALAR double complex
+#define SQRT_S csqrt
+#define FN(name) name##_c
+#include "element_body.inc"
+#undef SCALAR
+#undef SQRT_S
+#undef FN
+
+/* --------------------------------------------------------------- helpers */
+
+static int gather_element(int64_t nn, const double *x, const int32_t *conn, int64_t e,
+                          int32_t ids[4], double xe[4][3]) {
+    for (int a = 0; a < 4; ++a) {
+        int32_t n = conn[4 * e + a];
+        if (n < 0 || (int64_t)n >= nn) return 0;
+        ids[a] = n;
+        for (int i = 0; i < 3; ++i) xe[a][i] = x[3 * (int64_t)n + i];
+    }
+    return 1;
+}
+
+static void set_params(oracle_params *prm, double rho, double mu, double cs, const double *f) {
+    prm->rho = rho;
+    prm->mu = mu;
+    prm->cs = cs;
+    for (int i = 0; i < 3; ++i) prm->f[i] = f[i];
+}
+
+static int n_threads_or_default(int nthreads) {
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------ public API */
+
+/* Number of OpenMP threads a call with nthreads = 0 would use. */
+int oracle_default_threads(void) { return n_threads_or_default(0); }
+
+/* Per-element volume V_e and shape-function gradients gradN (ne x 4 x 3). */
+int oracle_geometry(int64_t nn, const double *x, int64_t ne, const int32_t *conn, double *vol,
+                    double *gradN) {
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t ids[4];
+        double xe[4][3], gN[4][3], V, D;
+        if (!gather_element(nn, x, conn, e, ids, xe)) return ORACLE_BAD_INDEX;
+        if (!element_geometry(xe, gN, &V, &D)) return ORACLE_DEGENERATE;
+        vol[e] = V;
+        memcpy(gradN + 12 * e, gN, sizeof gN);
+    }
+    return ORACLE_OK;
+}
+
+/* Per-element eddy viscosity mu_t (ne values). */
+int oracle_eddy(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
+                double rho, double mu, double cs, const double *f, double *mu_t) {
+    oracle_params prm;
+    set_params(&prm, rho, mu, cs, f);
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t ids[4];
+        double xe[4][3], gN[4][3], V, D, ue[4][3], pe[4] = {0, 0, 0, 0}, G[3][3], S[3][3], q[3], sm;
+        if (!gather_element(nn, x, conn, e, ids, xe)) return ORACLE_BAD_INDEX;
+        if (!element_geometry(xe, gN, &V, &D)) return ORACLE_DEGENERATE;
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i) ue[a][i] = u[3 * (int64_t)ids[a] + i];
+        gradients_r(gN, ue, pe, G, q);
+        mu_t[e] = eddy_viscosity_r(G, V, &prm, S, &sm);
+    }
+    return ORACLE_OK;
+}
+
+/* Assembled right-hand side rhs (nn x 3), FP64.  OpenMP over elements; each
+ * thread sums into a private copy of rhs, the copies are added at the end in
+ * thread order (deterministic for a fixed thread count). */
+int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
+               const double *p, double rho, double mu, double cs, const double *f, double *rhs,
+               int nthreads) {
+    oracle_params prm;
+    set_params(&prm, rho, mu, cs, f);
+    const int nt = n_threads_or_default(nthreads);
+    double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
+    if (!part) return ORACLE_NOMEM;
+    int status = ORACLE_OK;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        const int t = omp_get_thread_num();
+#else
+        const int t = 0;
+#endif
+        double *mine = part + (size_t)t * (size_t)nn * 3;
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t ids[4];
+            double xe[4][3], gN[4][3], V, D, ue[4][3], pe[4], re[4][3];
+            if (!gather_element(nn, x, conn, e, ids, xe)) {
+#pragma omp atomic write
+                status = ORACLE_BAD_INDEX;
+                continue;
+            }
+            if (!element_geometry(xe, gN, &V, &D)) {
+#pragma omp atomic write
+                status = ORACLE_DEGENERATE;
+                continue;
+            }
+            for (int a = 0; a < 4; ++a) {
+                for (int i = 0; i < 3; ++i) ue[a][i] = u[3 * (int64_t)ids[a] + i];
+                pe[a] = p[ids[a]];
+            }
+            element_rhs_r(gN, V, ue, pe, &prm, re);
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) mine[3 * (int64_t)ids[a] + i] += re[a][i];
+        }
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < nn * 3; ++k) {
+            double s = 0;
+            for (int tt = 0; tt < nt; ++tt) s += part[(size_t)tt * (size_t)nn * 3 + k];
+            rhs[k] = s;
+        }
+    }
+    free(part);
+    return status;
+}
+
+/* Complex-step form: velocity u_re + i u_im, real x and p; serial. */
+int oracle_rhs_complex(int64_t nn, const double *x, int64_t ne, const int32_t *conn,
+                       const double *u_re, const double *u_im, const double *p, double rho,
+                       double mu, double cs, const double *f, double *r_re, double *r_im) {
+    oracle_params prm;
+    set_params(&prm, rho, mu, cs, f);
+    double complex *acc = (double complex *)calloc((size_t)nn * 3, sizeof(double complex));
+    if (!acc) return ORACLE_NOMEM;
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t ids[4];
+        double xe[4][3], gN[4][3], V, D, pe[4];
+        double complex ue[4][3], re[4][3];
+        if (!gather_element(nn, x, conn, e, ids, xe)) { free(acc); return ORACLE_BAD_INDEX; }
+        if (!element_geometry(xe, gN, &V, &D)) { free(acc); return ORACLE_DEGENERATE; }
+        for (int a = 0; a < 4; ++a) {
+            for (int i = 0; i < 3; ++i) {
+                int64_t k = 3 * (int64_t)ids[a] + i;
+                ue[a][i] = u_re[k] + I * u_im[k];
+            }
+            pe[a] = p[ids[a]];
+        }
+        element_rhs_c(gN, V, ue, pe, &prm, re);
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i) acc[3 * (int64_t)ids[a] + i] += re[a][i];
+    }
+    for (int64_t k = 0; k < nn * 3; ++k) {
+        r_re[k] = creal(acc[k]);
+        r_im[k] = cimag(acc[k]);
+    }
+    free(acc);
+    return ORACLE_OK;
+}
+
+/* One element's velocity VJP contribution ge[b][k]. */
+static void element_vjp(const double gN[4][3], double V, const double ue[4][3],
+                        const double le[4][3], const oracle_params *prm, double ge[4][3]) {
+    const double pe[4] = {0, 0, 0, 0};
+    double G[3][3], S[3][3], q[3], smag;
+    gradients_r(gN, ue, pe, G, q);
+    const double mu_e = prm->mu + eddy_viscosity_r(G, V, prm, S, &smag);
+
+    double Lam[3][3]; /* Lambda_kj = sum_a lambda_{a,k} d_j N_a */
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int a = 0; a < 4; ++a) s += le[a][k] * gN[a][j];
+            Lam[k][j] = s;
+        }
+    double Phi = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Phi += Lam[i][j] * G[i][j];
+
+    for (int b = 0; b < 4; ++b)
+        for (int k = 0; k < 3; ++k) ge[b][k] = 0;
+
+    const double w = V / 4.0;
+    for (int g = 0; g < 4; ++g) {
+        double N[4], ug[3], lg[3];
+        for (int a = 0; a < 4; ++a) N[a] = (a == g) ? GAUSS_ALPHA : GAUSS_BETA;
+        for (int j = 0; j < 3; ++j) {
+            ug[j] = 0;
+            lg[j] = 0;
+            for (int a = 0; a < 4; ++a) {
+                ug[j] += N[a] * ue[a][j];
+                lg[j] += N[a] * le[a][j];
+            }
+        }
+        for (int b = 0; b < 4; ++b) {
+            double udn = 0;
+            for (int j = 0; j < 3; ++j) udn += ug[j] * gN[b][j];
+            for (int k = 0; k < 3; ++k) {
+                double gtl = 0;
+                for (int i = 0; i < 3; ++i) gtl += lg[i] * G[i][k];
+                ge[b][k] += -prm->rho * w * (N[b] * gtl + lg[k] * udn);
+            }
+        }
+    }
+    const double dmu_scale =
+        (prm->cs > 0.0 && smag != 0.0)
+            ? prm->rho * (prm->cs * cbrt(V)) * (prm->cs * cbrt(V)) * 2.0 / smag
+            : 0.0;
+    for (int b = 0; b < 4; ++b)
+        for (int k = 0; k < 3; ++k) {
+            double lv = 0, sv = 0;
+            for (int j = 0; j < 3; ++j) {
+                lv += gN[b][j] * Lam[k][j];
+                sv += S[k][j] * gN[b][j];
+            }
+            ge[b][k] += -mu_e * V * lv - V * Phi * dmu_scale * sv;
+        }
+}
+
+/* Velocity vector-Jacobian product g = (dR/du)^T lam (nn x 3), FP64, OpenMP as
+ * in oracle_rhs. */
+int oracle_vjp(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
+               const double *lam, double rho, double mu, double cs, const double *f, double *grad,
+               int nthreads) {
+    oracle_params prm;
+    set_params(&prm, rho, mu, cs, f);
+    const int nt = n_threads_or_default(nthreads);
+    double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
+    if (!part) return ORACLE_NOMEM;
+    int status = ORACLE_OK;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        const int t = omp_get_thread_num();
+#else
+        const int t = 0;
+#endif
+        double *mine = part + (size_t)t * (size_t)nn * 3;
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t ids[4];
+            double xe[4][3], gN[4][3], V, D, ue[4][3], le[4][3], ge[4][3];
+            if (!gather_element(nn, x, conn, e, ids, xe)) {
+#pragma omp atomic write
+                status = ORACLE_BAD_INDEX;
+                continue;
+            }
+            if (!element_geometry(xe, gN, &V, &D)) {
+#pragma omp atomic write
+                status = ORACLE_DEGENERATE;
+                continue;
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    ue[a][i] = u[3 * (int64_t)ids[a] + i];
+                    le[a][i] = lam[3 * (int64_t)ids[a] + i];
+                }
+            element_vjp(gN, V, ue, le, &prm, ge);
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) mine[3 * (int64_t)ids[a] + i] += ge[a][i];
+        }
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < nn * 3; ++k) {
+            double s = 0;
+            for (int tt = 0; tt < nt; ++tt) s += part[(size_t)tt * (size_t)nn * 3 + k];
+            grad[k] = s;
+        }
+    }
+    free(part);
+    return status;
+}

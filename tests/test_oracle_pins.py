@@ -1,0 +1,348 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle:
+exact rational integration, closed forms, textbook matrices, invariances and
+numerical differentiation.  CPU only."""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2403_08777_amd import synth
+
+F = np.array(synth.BODY_FORCE)
+
+
+def dyadic_mesh(n, jitter_seed=None):
+    """n^3 Kuhn cube whose coordinates are dyadic rationals (exact in FP64).
+    n must be a power of two; jittered interior nodes move by a multiple of
+    h/16 in [-3h/16, 3h/16]."""
+    m = synth.cube_mesh(n)
+    idx = np.rint(m.coords * n).astype(np.int64)  # lattice indices
+    coords = [[Fraction(int(c), n) for c in row] for row in idx]
+    if jitter_seed is not None:
+        rng = np.random.default_rng(jitter_seed)
+        for r, row in enumerate(idx):
+            if np.all((row > 0) & (row < n)):
+                d = rng.integers(-3, 4, 3)
+                coords[r] = [coords[r][i] + Fraction(int(d[i]), 16 * n) for i in range(3)]
+    xf = np.array([[float(c) for c in row] for row in coords])
+    return coords, m.conn, xf
+
+
+def dyadic_field(rng, nn, ncomp, scale=32):
+    vals = rng.integers(-2 * scale, 2 * scale + 1, (nn, ncomp))
+    return [[Fraction(int(v), scale) for v in row] for row in vals], vals / scale
+
+
+def frac_to_np(rows):
+    return np.array([[float(v) for v in row] for row in rows])
+
+
+def lumped_volume(coords, conn):
+    vol, _ = oracle.geometry(coords, conn)
+    vl = np.zeros(coords.shape[0])
+    np.add.at(vl, conn.reshape(-1), np.repeat(vol / 4.0, 4))
+    return vl
+
+
+def consistent_mass(coords, conn):
+    """Textbook P1-tetrahedron consistent mass matrix, M^e_ab = V (1 + d_ab) / 20,
+    with V from numpy's determinant."""
+    nn = coords.shape[0]
+    M = np.zeros((nn, nn))
+    for tet in conn:
+        J = (coords[tet[1:]] - coords[tet[0]]).T
+        V = abs(np.linalg.det(J)) / 6.0
+        for a in range(4):
+            for b in range(4):
+                M[tet[a], tet[b]] += V * (2.0 if a == b else 1.0) / 20.0
+    return M
+
+
+# ------------------------------------------------------------------ P1 exact
+
+@pytest.mark.parametrize("n,jit", [(2, None), (2, 11), (4, 12)])
+def test_exact_rational_forward(oracle_lib, n, jit):
+    coords, conn, xf = dyadic_mesh(n, jit)
+    rng = np.random.default_rng(100 + n)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    pq, pf = dyadic_field(rng, len(coords), 1)
+    pq = [row[0] for row in pq]
+    rho, mu = Fraction(5, 4), Fraction(3, 1000)
+    fq = [Fraction(1, 10), Fraction(-2, 10), Fraction(3, 10)]
+    ref = frac_to_np(exact.assemble_rhs(coords, conn, uq, pq, rho, mu, fq))
+    got = oracle.rhs(xf, conn, uf, pf[:, 0], oracle.Params(float(rho), float(mu), 0.0, F))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+def test_exact_rational_3cube(oracle_lib):
+    """Non-dyadic lattice (h = 1/3): exact checker on the exact mesh, oracle on
+    the rounded coordinates."""
+    m = synth.cube_mesh(3)
+    coords = [[Fraction(int(round(c * 3)), 3) for c in row] for row in m.coords]
+    rng = np.random.default_rng(7)
+    uq, uf = dyadic_field(rng, m.n_nodes, 3)
+    pq, pf = dyadic_field(rng, m.n_nodes, 1)
+    pq = [row[0] for row in pq]
+    fq = [Fraction(1, 10), Fraction(-2, 10), Fraction(3, 10)]
+    ref = frac_to_np(exact.assemble_rhs(coords, m.conn, uq, pq, Fraction(1), Fraction(1, 100), fq))
+    got = oracle.rhs(m.coords, m.conn, uf, pf[:, 0], oracle.Params(1.0, 0.01, 0.0, F))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+def test_exact_rational_eddy_linear_field(oracle_lib):
+    """Smagorinsky on: for a linear velocity every element's mu_t has a closed
+    form, rho (cs V^(1/3))^2 |S|, from the constant strain; the exact checker
+    with that per-element viscosity must reproduce the oracle."""
+    coords, conn, xf = dyadic_mesh(2, 21)
+    A = np.array([[0.5, 1.0, -0.25], [0.0, -0.75, 0.5], [0.25, 0.0, 0.25]])
+    c = np.array([0.125, -0.5, 0.25])
+    uf = xf @ A.T + c
+    Sm = 0.5 * (A + A.T)
+    smag = np.sqrt(2.0 * np.sum(Sm * Sm))
+    cs, rho, mu = 0.1, 1.0, 1e-4
+    vol_np = np.array([abs(np.linalg.det((xf[t[1:]] - xf[t[0]]).T)) / 6.0 for t in conn])
+    mu_elem = [Fraction(float(mu + rho * (cs * np.cbrt(v)) ** 2 * smag)) for v in vol_np]
+    uq = [[Fraction(float(v)) for v in row] for row in uf]
+    pz = [Fraction(0)] * len(coords)
+    fq = [Fraction(float(v)) for v in F]
+    ref = frac_to_np(exact.assemble_rhs(coords, conn, uq, pz, Fraction(1), Fraction(0), fq, mu_elem))
+    got = oracle.rhs(xf, conn, uf, np.zeros(len(coords)), oracle.Params(rho, mu, cs, F))
+    assert oracle.rel_l2(got, ref) < 1e-13
+
+
+# --------------------------------------------------------------- P2 geometry
+
+@pytest.mark.parametrize("jitter", [False, True])
+def test_geometry(oracle_lib, jitter):
+    m = synth.cube_mesh(4, jitter=jitter, permute=True)
+    vol, gn = oracle.geometry(m.coords, m.conn)
+    assert abs(vol.sum() - 1.0) < 1e-13
+    for e in range(m.n_elems):
+        xe = m.coords[m.conn[e]]
+        # sum_a x_a (x) grad N_a = I : the gradients reproduce linear functions
+        np.testing.assert_allclose(xe.T @ gn[e], np.eye(3), atol=1e-12)
+        J = (xe[1:] - xe[0]).T
+        np.testing.assert_allclose(gn[e, 1:], np.linalg.inv(J), rtol=1e-12, atol=1e-12)
+        assert abs(vol[e] - abs(np.linalg.det(J)) / 6) < 1e-15
+
+
+def test_kuhn_split_orientation_mixed():
+    """Half the Kuhn tets are negatively oriented in natural vertex order, so
+    the volume must use |det J|."""
+    m = synth.cube_mesh(1)
+    dets = [np.linalg.det((m.coords[t[1:]] - m.coords[t[0]]).T) for t in m.conn]
+    assert sum(d > 0 for d in dets) == 3 and sum(d < 0 for d in dets) == 3
+
+
+# ------------------------------------------------------------ P3 convective
+
+def test_convective_linear_field_closed_form(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 3))
+    c = rng.standard_normal(3)
+    u = m.coords @ A.T + c
+    rho = 1.3
+    got = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), oracle.Params(rho, 0.0, 0.0, (0, 0, 0)))
+    M = consistent_mass(m.coords, m.conn)
+    ref = -rho * M @ (u @ A.T)
+    assert oracle.rel_l2(got, ref) < 1e-13
+
+
+def test_convective_constant_field_is_zero(oracle_lib):
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    u = np.tile([0.3, -1.2, 2.5], (m.n_nodes, 1))
+    got = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), oracle.Params(1.0, 0.0, 0.0, (0, 0, 0)))
+    assert np.abs(got).max() < 1e-13
+
+
+# --------------------------------------------------------------- P4 viscous
+
+def test_viscous_sums_to_zero_and_kills_linear(oracle_lib):
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    rng = np.random.default_rng(6)
+    u = rng.standard_normal((m.n_nodes, 3))
+    prm = oracle.Params(0.0, 0.7, 0.0, (0, 0, 0))
+    r = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), prm)
+    assert np.abs(r.sum(axis=0)).max() < 1e-12 * np.abs(r).max()
+    A = rng.standard_normal((3, 3))
+    ul = m.coords @ A.T
+    r = oracle.rhs(m.coords, m.conn, ul, np.zeros(m.n_nodes), prm)
+    lat = np.rint(m.lattice_xyz * 4)
+    interior_lattice = np.all((lat > 0) & (lat < 4), axis=1)
+    interior_user = m.perm[interior_lattice]
+    assert np.abs(r[interior_user]).max() < 1e-13
+
+
+def test_viscous_seven_point_stencil(oracle_lib):
+    """On the unjittered Kuhn lattice the P1 stiffness is the 7-point stencil
+    times h, so u = (x^2, 0, 0) gives mu * 2 h^3 at interior nodes."""
+    n, mu = 6, 0.37
+    m = synth.cube_mesh(n)
+    u = np.zeros((m.n_nodes, 3))
+    u[:, 0] = m.coords[:, 0] ** 2
+    r = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), oracle.Params(0.0, mu, 0.0, (0, 0, 0)))
+    lat = np.rint(m.coords * n)
+    interior = np.all((lat > 0) & (lat < n), axis=1)
+    np.testing.assert_allclose(r[interior, 0], 2 * mu / n ** 3, rtol=1e-12)
+    assert np.abs(r[interior, 1:]).max() < 1e-15
+
+
+# ----------------------------------------------------- P5, P6 pressure, body
+
+def test_pressure_terms(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    prm = oracle.Params(0.0, 0.0, 0.0, (0, 0, 0))
+    u0 = np.zeros((m.n_nodes, 3))
+    r = oracle.rhs(m.coords, m.conn, u0, np.full(m.n_nodes, 4.2), prm)
+    assert np.abs(r).max() < 1e-14
+    q = np.array([0.3, -1.1, 0.8])
+    r = oracle.rhs(m.coords, m.conn, u0, m.coords @ q + 2.0, prm)
+    vl = lumped_volume(m.coords, m.conn)
+    np.testing.assert_allclose(r, -np.outer(vl, q), rtol=1e-12, atol=1e-16)
+
+
+def test_body_force(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    rho = 1.7
+    r = oracle.rhs(m.coords, m.conn, np.zeros((m.n_nodes, 3)), np.zeros(m.n_nodes),
+                   oracle.Params(rho, 0.5, 0.1, F))
+    vl = lumped_volume(m.coords, m.conn)
+    np.testing.assert_allclose(r, rho * np.outer(vl, F), rtol=1e-13)
+    np.testing.assert_allclose(r.sum(axis=0), rho * F, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- P7 eddy
+
+def test_eddy_viscosity_closed_forms(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True)
+    vol, _ = oracle.geometry(m.coords, m.conn)
+    rho, cs = 1.3, 0.1
+    gamma = -2.5
+    shear = np.zeros((m.n_nodes, 3))
+    shear[:, 0] = gamma * m.coords[:, 1]
+    mu_t = oracle.eddy(m.coords, m.conn, shear, oracle.Params(rho, 0.0, cs))
+    np.testing.assert_allclose(mu_t, rho * (cs * np.cbrt(vol)) ** 2 * abs(gamma), rtol=1e-12)
+    a = 0.8  # pure strain (a x, -a y, 0): |S| = 2|a|
+    strain = np.stack([a * m.coords[:, 0], -a * m.coords[:, 1], 0 * m.coords[:, 2]], axis=1)
+    mu_t = oracle.eddy(m.coords, m.conn, strain, oracle.Params(rho, 0.0, cs))
+    np.testing.assert_allclose(mu_t, rho * (cs * np.cbrt(vol)) ** 2 * 2 * a, rtol=1e-12)
+    w = np.array([0.4, -1.0, 2.0])  # rigid rotation w x x: no strain, no eddy viscosity
+    rot = np.cross(w, m.coords)
+    mu_t = oracle.eddy(m.coords, m.conn, rot, oracle.Params(rho, 0.0, cs))
+    assert np.abs(mu_t).max() < 1e-15
+    mu_t = oracle.eddy(m.coords, m.conn, shear, oracle.Params(rho, 0.0, 0.0))
+    assert np.all(mu_t == 0)
+
+
+# ---------------------------------------------------------- P8 invariance
+
+def test_translation_rotation_invariance(oracle_lib):
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F)
+    r = oracle.rhs(m.coords, m.conn, u, p, prm)
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    t = rng.standard_normal(3)
+    r2 = oracle.rhs(m.coords @ Q.T + t, m.conn, u @ Q.T, p, oracle.Params(1.0, 1e-3, 0.1, Q @ F))
+    assert oracle.rel_l2(r2, r @ Q.T) < 1e-13
+
+
+# ---------------------------------------------------------- P9 relabelling
+
+def test_relabelling(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True)
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F)
+    r = oracle.rhs(m.coords, m.conn, u, p, prm)
+    rng = np.random.default_rng(9)
+    perm = rng.permutation(m.n_nodes)  # new id of old node
+    coords2 = np.empty_like(m.coords)
+    coords2[perm] = m.coords
+    u2 = np.empty_like(u)
+    u2[perm] = u
+    p2 = np.empty_like(p)
+    p2[perm] = p
+    conn2 = perm[m.conn][rng.permutation(m.n_elems)]
+    conn2 = np.array([row[rng.permutation(4)] for row in conn2], dtype=np.int32)
+    r2 = oracle.rhs(coords2, conn2, u2, p2, prm)
+    assert oracle.rel_l2(r2[perm], r) < 1e-14
+
+
+# ----------------------------------------------------------------- VJP pins
+
+def test_vjp_exact_rational(oracle_lib):
+    coords, conn, xf = dyadic_mesh(2, 31)
+    rng = np.random.default_rng(32)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    lq, lf = dyadic_field(rng, len(coords), 3)
+    rho, mu = Fraction(3, 2), Fraction(1, 64)
+    fq = [Fraction(0)] * 3
+    ref = frac_to_np(exact.assemble_vjp(coords, conn, uq, lq, rho, mu, fq))
+    got = oracle.vjp(xf, conn, uf, lf, oracle.Params(float(rho), float(mu), 0.0, F))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("cs", [0.0, 0.1])
+def test_vjp_complex_step_dense_jacobian(oracle_lib, cs):
+    m = synth.cube_mesh(2, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    prm = oracle.Params(1.0, 1e-3, cs, F)
+    jac = oracle.dense_jacobian_complex_step(m.coords, m.conn, u, p, prm)
+    g_ref = (jac.T @ lam.reshape(-1)).reshape(-1, 3)
+    g = oracle.vjp(m.coords, m.conn, u, lam, prm)
+    assert oracle.rel_l2(g, g_ref) < 1e-12
+
+
+def test_complex_step_matches_central_difference(oracle_lib):
+    """Independent check of the complex-step machinery itself."""
+    m = synth.cube_mesh(2, jitter=True)
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F)
+    d = np.random.default_rng(12).standard_normal(u.shape)
+    jac = oracle.dense_jacobian_complex_step(m.coords, m.conn, u, p, prm)
+    h = 1e-6
+    fd = (oracle.rhs(m.coords, m.conn, u + h * d, p, prm) - oracle.rhs(m.coords, m.conn, u - h * d, p, prm)) / (2 * h)
+    assert oracle.rel_l2(fd.reshape(-1), jac @ d.reshape(-1)) < 1e-7
+
+
+@pytest.mark.parametrize("cs,mu", [(0.0, 1e-3), (0.1, 1e-4)])
+def test_vjp_central_fd_16(oracle_lib, cs, mu):
+    m = synth.cube_mesh(16, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    prm = oracle.Params(1.0, mu, cs, F)
+    d = np.random.default_rng(5).standard_normal(u.shape)
+    h = 1e-6
+    rp = oracle.rhs(m.coords, m.conn, u + h * d, p, prm)
+    rm = oracle.rhs(m.coords, m.conn, u - h * d, p, prm)
+    fd = (np.sum(lam * rp) - np.sum(lam * rm)) / (2 * h)
+    g = oracle.vjp(m.coords, m.conn, u, lam, prm)
+    gd = np.sum(g * d)
+    assert abs(fd - gd) <= 1e-6 * abs(gd)
+
+
+def test_oracle_errors(oracle_lib):
+    m = synth.cube_mesh(1)
+    bad = m.conn.copy()
+    bad[0, 0] = m.n_nodes
+    with pytest.raises(ValueError, match="out of range"):
+        oracle.rhs(m.coords, bad, np.zeros((m.n_nodes, 3)), np.zeros(m.n_nodes), oracle.Params())
+    flat = m.coords.copy()
+    flat[:, 2] = 0.0
+    with pytest.raises(ValueError, match="degenerate"):
+        oracle.rhs(flat, m.conn, np.zeros((m.n_nodes, 3)), np.zeros(m.n_nodes), oracle.Params())
+
+
+def test_thread_count_independence(oracle_lib):
+    m = synth.cube_mesh(6, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-4, 0.1, F)
+    r1 = oracle.rhs(m.coords, m.conn, u, p, prm, nthreads=1)
+    r4 = oracle.rhs(m.coords, m.conn, u, p, prm, nthreads=4)
+    assert oracle.rel_l2(r4, r1) < 1e-15
