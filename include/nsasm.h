@@ -1,0 +1,194 @@
+/*
+ * nsasm -- element-by-element assembly of the incompressible Navier-Stokes
+ * momentum right-hand side over linear tetrahedra, on one AMD MI355X (gfx950).
+ *
+ * The operation is the RHS assembly of an explicit-momentum fractional-step LES
+ * (Owen, Ernst et al., "Alya towards Exascale", Sec. II), specialised as in
+ * Sec. IV-B: linear tetrahedra (4 nodes, constant shape-function gradients),
+ * constant density and viscosity, an eddy viscosity evaluated once per element
+ * on the fly, and the elemental RHS computed directly without elemental
+ * matrices (Sec. IV-A).  For element e with vertices a = 0..3 and nodal
+ * velocity u_a, pressure p_a:
+ *
+ *   J = [x1-x0 | x2-x0 | x3-x0],  V = |det J| / 6,
+ *   grad N_a = row a of J^-1 (a = 1..3),  grad N_0 = -(grad N_1 + grad N_2 + grad N_3),
+ *   G = grad u = sum_a u_a (x) grad N_a,  q = grad p = sum_a p_a grad N_a,
+ *   mu_e = mu + rho (cs V^(1/3))^2 |S|,  S = (G + G^T)/2,  |S| = sqrt(2 S:S),
+ *   R^e_a = int_e N_a (-rho G u_h - q + rho f) dx - mu_e V G grad N_a,
+ *   rhs_n = sum over (e, a) with node(e, a) = n of R^e_a,
+ *
+ * where u_h is the P1 interpolant and the integral is the 4-point Gauss rule
+ * (exact here, since the integrand has degree 2).  The paper prints no
+ * discrete equations; the forms above (advective convection, gradient-form
+ * pressure, Laplacian viscous term, Smagorinsky eddy viscosity, constant body
+ * acceleration) are this library's reading of it.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (hipMalloc / torch CUDA tensors) on
+ *    the current device; host pointers are rejected with
+ *    NSASM_ERR_INVALID_ARGUMENT.  Arrays are dense, row-major, 64-bit indexed.
+ *  - Field element type: double for NSASM_FP64, float for NSASM_MIXED.
+ *    Coordinates are always double.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Assembly calls are
+ *    asynchronous on it and report launch errors only.  nsasm_mesh_create is
+ *    synchronous.
+ *  - The caller owns every argument buffer; the library keeps no caller
+ *    pointer.  A mesh owns its internal device buffers until destroyed.
+ *  - No call throws or aborts; each returns an nsasm_status and, when it is
+ *    not NSASM_OK, sets a thread-local message read by nsasm_last_error().
+ *  - A mesh is immutable after creation: concurrent assembly calls on one mesh
+ *    are safe when their output buffers differ.
+ */
+#ifndef NSASM_H
+#define NSASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsasm_mesh nsasm_mesh; /* opaque, immutable after create */
+
+typedef enum {
+    NSASM_OK = 0,
+    NSASM_ERR_INVALID_ARGUMENT = 1,   /* null/host pointer, bad size, bad enum */
+    NSASM_ERR_BAD_CONNECTIVITY = 2,   /* node id out of range or repeated in a tet */
+    NSASM_ERR_DEGENERATE_ELEMENT = 3, /* det J == 0 (or not finite) */
+    NSASM_ERR_OUT_OF_MEMORY = 4,
+    NSASM_ERR_DEVICE = 5,             /* HIP runtime / launch failure */
+    NSASM_ERR_UNSUPPORTED = 6         /* valid request the mesh cannot serve */
+} nsasm_status;
+
+typedef enum {
+    NSASM_FP64 = 0,  /* all arithmetic and fields in double */
+    NSASM_MIXED = 1  /* geometry (det J, J^-1, V) in double; fields, element
+                        arithmetic and scatter-add in float */
+} nsasm_precision;
+
+typedef enum {
+    NSASM_SCATTER_AUTO = 0,   /* PATCH when the mesh allows it, else ATOMIC */
+    NSASM_SCATTER_ATOMIC = 1, /* one thread per element, 12 global atomic adds */
+    NSASM_SCATTER_PATCH = 2   /* element patches staged through LDS: nodes gathered
+                                 once per patch, element sums reduced in LDS, one
+                                 global atomic add per patch node and component */
+} nsasm_scatter;
+
+/* Set in nsasm_params.flags: add into the output instead of overwriting it. */
+#define NSASM_ACCUMULATE 1u
+
+typedef struct {
+    double rho;            /* density, constant (> 0) */
+    double mu;             /* molecular dynamic viscosity, constant (>= 0) */
+    double smagorinsky_cs; /* Smagorinsky constant; 0 disables the eddy viscosity */
+    double body_force[3];  /* constant body-force acceleration f; term is +rho f */
+    uint32_t flags;        /* bitwise OR of NSASM_ACCUMULATE, or 0 */
+    uint32_t reserved;     /* must be 0 */
+} nsasm_params;
+
+typedef struct {
+    int32_t renumber;    /* 1 (default): sort elements along a Morton curve and
+                            renumber nodes by first touch; 0: keep user order */
+    int32_t scatter;     /* nsasm_scatter */
+    int32_t patch_elems; /* elements per patch, 32..256 in steps of 32 (0 = 256) */
+    int32_t reserved;    /* must be 0 */
+} nsasm_mesh_options;
+
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_elems;
+    int32_t scatter;         /* resolved nsasm_scatter: ATOMIC or PATCH */
+    int32_t renumbered;      /* 1 if mesh order differs from user order */
+    int32_t n_patches;       /* 0 when scatter == ATOMIC */
+    int32_t patch_elems;
+    int32_t max_patch_nodes; /* largest number of distinct nodes in one patch */
+    int32_t reserved;
+    int64_t patch_node_refs; /* sum over patches of their distinct nodes */
+} nsasm_mesh_info_t;
+
+/*
+ * Build a mesh: validate the connectivity, then (renumber = 1) order elements
+ * along a Morton curve of their centroids, renumber nodes in order of first
+ * use by that element order, and cut the element sequence into patches.
+ * Locality of nodal gathers and scatters is what this buys (Sec. IV-C:
+ * indirect nodal accesses dominate once intermediates live in registers, and
+ * nodal reuse happens in the cache shared by the threads).
+ *
+ * coords  : device, n_nodes x 3 doubles, user node order.
+ * conn    : device, n_elems x 4 int32 node ids in [0, n_nodes), 4 distinct per
+ *           element; local vertex order and orientation are free.
+ * opts    : may be NULL (defaults above).
+ * out     : receives the handle; set to NULL on failure (nothing is leaked).
+ * Errors  : INVALID_ARGUMENT (null/host pointers, n <= 0, n_nodes >= 2^31,
+ *           n_elems >= 2^29, bad options), BAD_CONNECTIVITY, DEGENERATE_ELEMENT,
+ *           OUT_OF_MEMORY, DEVICE; UNSUPPORTED when scatter = PATCH is asked for
+ *           and some patch has more than 256 distinct nodes.
+ */
+nsasm_status nsasm_mesh_create(const double *coords, int64_t n_nodes, const int32_t *conn,
+                               int64_t n_elems, const nsasm_mesh_options *opts, void *stream,
+                               nsasm_mesh **out);
+
+/* Free a mesh and its device buffers (synchronises the device).  NULL is OK. */
+nsasm_status nsasm_mesh_destroy(nsasm_mesh *mesh);
+
+/* Sizes and layout decisions of a mesh (host struct). */
+nsasm_status nsasm_mesh_info(const nsasm_mesh *mesh, nsasm_mesh_info_t *info);
+
+/* mesh_id_of_user: device, n_nodes int32; entry k is the mesh-order index of
+ * user node k (identity when not renumbered).  Asynchronous on stream. */
+nsasm_status nsasm_mesh_permutation(const nsasm_mesh *mesh, int32_t *mesh_id_of_user, void *stream);
+
+/* Internal connectivity: conn_mesh (device, n_elems x 4 int32, mesh node ids,
+ * mesh element order) and user_elem (device, n_elems int32, user index of each
+ * mesh-order element).  Either may be NULL.  Asynchronous on stream. */
+nsasm_status nsasm_mesh_connectivity(const nsasm_mesh *mesh, int32_t *conn_mesh, int32_t *user_elem,
+                                     void *stream);
+
+/* Reorder a per-node field with ncomp (1..16) components between user order
+ * and mesh order: mesh_ordered[perm[k]] = user[k] and back.  Element type per
+ * precision (double / float).  Buffers must not overlap.  Asynchronous. */
+nsasm_status nsasm_to_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_precision precision,
+                                 const void *user, void *mesh_ordered, void *stream);
+nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_precision precision,
+                                   const void *mesh_ordered, void *user, void *stream);
+
+/*
+ * Assemble the momentum RHS (definition at the top of this file).
+ * u   : device, n_nodes x 3, mesh order.    p : device, n_nodes, mesh order.
+ * rhs : device, n_nodes x 3, mesh order; overwritten (or added to with
+ *       NSASM_ACCUMULATE).  Must not overlap u or p.
+ * Summation order across elements is unspecified (atomic adds), so results
+ * may differ between calls by rounding.  Asynchronous on stream.
+ * Errors: INVALID_ARGUMENT (null/host pointers, rho <= 0, mu < 0, cs < 0,
+ * non-finite parameters, unknown precision or flags), DEVICE.
+ */
+nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
+                                nsasm_precision precision, const void *u, const void *p, void *rhs,
+                                void *stream);
+
+/*
+ * Velocity vector-Jacobian product of the assembled RHS:
+ *   grad_u = (d rhs / d u)^T adjoint,
+ * recomputing the element quantities (nothing is stored by the forward call).
+ * The pressure and body-force terms do not depend on u.  With cs > 0 the
+ * derivative of mu_t uses d|S|/dG = 2 S / |S|, taken as 0 where |S| = 0.
+ * u, adjoint : device, n_nodes x 3, mesh order.
+ * grad_u     : device, n_nodes x 3, mesh order; overwritten (or added to with
+ *              NSASM_ACCUMULATE).  Must not overlap the inputs.
+ * Errors and ordering as nsasm_assemble_rhs.
+ */
+nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *params,
+                                    nsasm_precision precision, const void *u, const void *adjoint,
+                                    void *grad_u, void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *nsasm_last_error(void);
+
+/* Library version string, e.g. "0.1.0". */
+const char *nsasm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSASM_H */

@@ -1,0 +1,467 @@
+// Momentum right-hand-side assembly over linear tetrahedra and its velocity
+// vector-Jacobian product: element math and the two scatter strategies.
+//
+// Element math (one thread per element, everything in registers):
+//   geometry in FP64: J columns d_k = x_k - x_0, rows of adj(J) c_1 = d_2 x d_3,
+//   c_2 = d_3 x d_1, c_3 = d_1 x d_2, det J = d_1 . c_1, grad N_k = c_k / det J,
+//   grad N_0 = -(grad N_1 + grad N_2 + grad N_3), V = |det J| / 6.
+//
+//   The paper integrates with four Gauss points on P1 tetrahedra (Sec. IV-B).
+//   Because grad N, G = grad u and q = grad p are constant on the element, the
+//   Gauss sums collapse exactly: with N_a(g) = alpha (a == g) or beta, weight
+//   V/4, one has sum_g (V/4) N_a(g) = V/4 and sum_g (V/4) N_a(g) N_b(g) =
+//   (V/4)(alpha^2 + 3 beta^2) = V/10 for a == b, (V/4)(2 alpha beta + 2 beta^2)
+//   = V/20 otherwise.  So
+//     sum_g (V/4) N_a(g) [-rho G u^g - q + rho f]
+//       = -(rho V / 20) G (u_a + U) + (V/4)(rho f - q),   U = sum_b u_b,
+//   and adding the viscous term -mu_e V G grad N_a gives
+//     R^e_a = b - G y_a,   b = (V/4)(rho f - q),
+//     y_a = (rho V / 20)(u_a + U) + mu_e V grad N_a.
+//   This is the paper's restructuring (compute each RHS entry directly, few
+//   live intermediates; Sec. IV-A) carried one step further: the four Gauss
+//   points are summed symbolically, not numerically.
+//
+//   VJP, g = (dR/du)^T lambda, per element with L = sum_a lambda_a,
+//   P = sum_a lambda_a (x) u_a, Lambda = sum_a lambda_a (x) grad N_a:
+//     g_b = -M grad N_b - (rho V / 20) G^T (lambda_b + L),
+//     M = (rho V / 20)(P + L (x) U) + mu_e V Lambda + V Phi kappa S,
+//   where Phi = Lambda : G and kappa = rho (cs Delta)^2 2 / |S| (0 if |S| = 0)
+//   is the derivative of the Smagorinsky viscosity.
+//
+// Scatter strategies:
+//   ATOMIC: one thread per element, 12 global atomic adds.
+//   PATCH:  one workgroup per patch of <= 256 consecutive (Morton-ordered)
+//           elements; the patch's <= 256 distinct nodes are loaded once into
+//           LDS, element contributions are summed with LDS atomics, and each
+//           patch node gets one global atomic add per component.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace nsasm {
+namespace {
+
+constexpr int kThreads = 256;
+enum Mode { kForward = 0, kVjp = 1 };
+
+template <typename T>
+struct KParams {
+    T rho;
+    T mu;
+    T rho_cs2;     // rho * cs^2
+    T rho_f[3];    // rho * f
+};
+
+// ------------------------------------------------------------ atomics
+
+__device__ inline void global_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void global_add(float *p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_add(float *p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline double cube_root(double v) { return cbrt(v); }
+__device__ inline float cube_root(float v) { return cbrtf(v); }
+
+// ----------------------------------------------------------- element math
+
+// Shape-function gradients and volume, always in FP64.
+__device__ inline void tet_geometry(const double (&xe)[4][3], double (&gN)[4][3], double &vol) {
+    double d1[3], d2[3], d3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d1[i] = xe[1][i] - xe[0][i];
+        d2[i] = xe[2][i] - xe[0][i];
+        d3[i] = xe[3][i] - xe[0][i];
+    }
+    const double c1[3] = {d2[1] * d3[2] - d2[2] * d3[1], d2[2] * d3[0] - d2[0] * d3[2],
+                          d2[0] * d3[1] - d2[1] * d3[0]};
+    const double c2[3] = {d3[1] * d1[2] - d3[2] * d1[1], d3[2] * d1[0] - d3[0] * d1[2],
+                          d3[0] * d1[1] - d3[1] * d1[0]};
+    const double c3[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2],
+                          d1[0] * d2[1] - d1[1] * d2[0]};
+    const double det = d1[0] * c1[0] + d1[1] * c1[1] + d1[2] * c1[2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        gN[1][i] = c1[i] * inv;
+        gN[2][i] = c2[i] * inv;
+        gN[3][i] = c3[i] * inv;
+        gN[0][i] = -(gN[1][i] + gN[2][i] + gN[3][i]);
+    }
+    vol = fabs(det) * (1.0 / 6.0);
+}
+
+// G[i][j] = d v_i / d x_j for a nodal vector field v.
+template <typename T>
+__device__ inline void vector_gradient(const T (&gN)[4][3], const T (&ve)[4][3], T (&G)[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T d1 = ve[1][i] - ve[0][i], d2 = ve[2][i] - ve[0][i], d3 = ve[3][i] - ve[0][i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G[i][j] = d1 * gN[1][j] + d2 * gN[2][j] + d3 * gN[3][j];
+    }
+}
+
+// Smagorinsky: |S| with S = (G + G^T)/2, |S| = sqrt(2 S:S); returns S too.
+template <typename T>
+__device__ inline T strain_norm(const T (&G)[3][3], T (&S)[3][3]) {
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            S[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+            ss += S[i][j] * S[i][j];
+        }
+    return sqrt(T(2) * ss);
+}
+
+template <typename T, bool EDDY>
+__device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&pe)[4],
+                                   const KParams<T> &P, T (&re)[4][3]) {
+    T G[3][3];
+    vector_gradient(gN, ue, G);
+    T q[3];
+    {
+        const T d1 = pe[1] - pe[0], d2 = pe[2] - pe[0], d3 = pe[3] - pe[0];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[j] = d1 * gN[1][j] + d2 * gN[2][j] + d3 * gN[3][j];
+    }
+    T mu_e = P.mu;
+    if (EDDY) {
+        T S[3][3];
+        const T smag = strain_norm(G, S);
+        const T delta = cube_root(vol);
+        mu_e += P.rho_cs2 * delta * delta * smag;
+    }
+    const T sc = P.rho * vol * T(0.05);
+    const T sv = mu_e * vol;
+    const T w4 = vol * T(0.25);
+    T U[3], b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
+        b[i] = w4 * (P.rho_f[i] - q[i]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        T y[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) y[j] = sc * (ue[a][j] + U[j]) + sv * gN[a][j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) re[a][i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
+    }
+}
+
+template <typename T, bool EDDY>
+__device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
+                                   const KParams<T> &P, T (&ge)[4][3]) {
+    T G[3][3], Lam[3][3];
+    vector_gradient(gN, ue, G);
+    vector_gradient(gN, le, Lam);
+    T mu_e = P.mu;
+    const T sc = P.rho * vol * T(0.05);
+    T U[3], L[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
+        L[i] = le[0][i] + le[1][i] + le[2][i] + le[3][i];
+    }
+    T M[3][3];
+    if (EDDY) {
+        T S[3][3];
+        const T smag = strain_norm(G, S);
+        const T delta = cube_root(vol);
+        const T c = P.rho_cs2 * delta * delta;
+        mu_e += c * smag;
+        T phi = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) phi += Lam[i][j] * G[i][j];
+        const T kappa = (smag > T(0)) ? T(2) * c / smag : T(0);
+        const T se = vol * phi * kappa;
+        const T sv = mu_e * vol;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] +
+                              le[3][k] * ue[3][j];
+                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j] + se * S[k][j];
+            }
+    } else {
+        const T sv = mu_e * vol;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] +
+                              le[3][k] * ue[3][j];
+                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
+            }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const T w0 = le[b][0] + L[0], w1 = le[b][1] + L[1], w2 = le[b][2] + L[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            ge[b][k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) -
+                       sc * (G[0][k] * w0 + G[1][k] * w1 + G[2][k] * w2);
+    }
+}
+
+template <typename T>
+__device__ inline void to_field(const double (&g64)[4][3], double vol64, T (&gN)[4][3], T &vol) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) gN[a][i] = static_cast<T>(g64[a][i]);
+    vol = static_cast<T>(vol64);
+}
+
+// ------------------------------------------------------------- kernels
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_zero(T *p, int64_t n) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * kThreads)
+        p[k] = T(0);
+}
+
+// One thread per element; f0 = u, f1 = p (forward) or lambda (VJP).
+template <typename T, bool EDDY, int MODE>
+__global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const int4 *__restrict__ conn,
+                                                               const double *__restrict__ x,
+                                                               const T *__restrict__ f0,
+                                                               const T *__restrict__ f1, KParams<T> P,
+                                                               T *__restrict__ out) {
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t e = tile * kThreads + threadIdx.x;
+    if (e >= ne) return;
+    const int4 c = conn[e];
+    const int64_t ids[4] = {c.x, c.y, c.z, c.w};
+    double xe[4][3];
+    T ue[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            xe[a][i] = x[3 * ids[a] + i];
+            ue[a][i] = f0[3 * ids[a] + i];
+        }
+    double g64[4][3], vol64;
+    tet_geometry(xe, g64, vol64);
+    T gN[4][3], vol;
+    to_field(g64, vol64, gN, vol);
+    T r[4][3];
+    if (MODE == kForward) {
+        T pe[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pe[a] = f1[ids[a]];
+        element_rhs<T, EDDY>(gN, vol, ue, pe, P, r);
+    } else {
+        T le[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) le[a][i] = f1[3 * ids[a] + i];
+        element_vjp<T, EDDY>(gN, vol, ue, le, P, r);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) global_add(&out[3 * ids[a] + i], r[a][i]);
+}
+
+// One workgroup per patch (see the file header).
+template <typename T, bool EDDY, int MODE>
+__global__ __launch_bounds__(kThreads) void k_assemble_patch(
+    int64_t ne, int32_t n_patches, int32_t patch_elems, const int32_t *__restrict__ patch_off,
+    const int32_t *__restrict__ patch_nodes, const uint32_t *__restrict__ lconn,
+    const double *__restrict__ x, const T *__restrict__ f0, const T *__restrict__ f1, KParams<T> P,
+    T *__restrict__ out) {
+    constexpr int kF1 = (MODE == kForward) ? 1 : 3;
+    __shared__ double sx[3][kMaxPatchNodes];
+    __shared__ T su[3][kMaxPatchNodes];
+    __shared__ T s1[kF1][kMaxPatchNodes];
+    __shared__ T sacc[3][kMaxPatchNodes];
+
+    const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
+    if (patch >= n_patches) return;
+    const int t = threadIdx.x;
+    const int32_t beg = patch_off[patch];
+    const int32_t cnt = patch_off[patch + 1] - beg;
+    int64_t node = 0;
+    if (t < cnt) {
+        node = patch_nodes[beg + t];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sx[i][t] = x[3 * node + i];
+            su[i][t] = f0[3 * node + i];
+            sacc[i][t] = T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < kF1; ++i) s1[i][t] = f1[kF1 * node + i];
+    }
+    __syncthreads();
+
+    const int64_t e = static_cast<int64_t>(patch) * patch_elems + t;
+    if (t < patch_elems && e < ne) {
+        const uint32_t lc = lconn[e];
+        const int la[4] = {static_cast<int>(lc & 0xff), static_cast<int>((lc >> 8) & 0xff),
+                           static_cast<int>((lc >> 16) & 0xff), static_cast<int>(lc >> 24)};
+        double xe[4][3];
+        T ue[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                xe[a][i] = sx[i][la[a]];
+                ue[a][i] = su[i][la[a]];
+            }
+        double g64[4][3], vol64;
+        tet_geometry(xe, g64, vol64);
+        T gN[4][3], vol;
+        to_field(g64, vol64, gN, vol);
+        T r[4][3];
+        if (MODE == kForward) {
+            T pe[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pe[a] = s1[0][la[a]];
+            element_rhs<T, EDDY>(gN, vol, ue, pe, P, r);
+        } else {
+            T le[4][3];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) le[a][i] = s1[i][la[a]];
+            element_vjp<T, EDDY>(gN, vol, ue, le, P, r);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) lds_add(&sacc[i][la[a]], r[a][i]);
+    }
+    __syncthreads();
+    if (t < cnt) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) global_add(&out[3 * node + i], sacc[i][t]);
+    }
+}
+
+// ---------------------------------------------------------- host side
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+nsasm_status check_params(const nsasm_params *p) {
+    if (!p) return fail(NSASM_ERR_INVALID_ARGUMENT, "params is NULL");
+    const double vals[6] = {p->rho, p->mu, p->smagorinsky_cs, p->body_force[0], p->body_force[1],
+                            p->body_force[2]};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(NSASM_ERR_INVALID_ARGUMENT, "parameters must be finite");
+    if (!(p->rho > 0.0)) return fail(NSASM_ERR_INVALID_ARGUMENT, "rho must be > 0");
+    if (p->mu < 0.0) return fail(NSASM_ERR_INVALID_ARGUMENT, "mu must be >= 0");
+    if (p->smagorinsky_cs < 0.0) return fail(NSASM_ERR_INVALID_ARGUMENT, "smagorinsky_cs must be >= 0");
+    if (p->flags & ~NSASM_ACCUMULATE) return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
+    if (p->reserved != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "reserved must be 0");
+    return NSASM_OK;
+}
+
+template <typename T>
+KParams<T> kernel_params(const nsasm_params &p) {
+    KParams<T> k;
+    k.rho = static_cast<T>(p.rho);
+    k.mu = static_cast<T>(p.mu);
+    k.rho_cs2 = static_cast<T>(p.rho * p.smagorinsky_cs * p.smagorinsky_cs);
+    for (int i = 0; i < 3; ++i) k.rho_f[i] = static_cast<T>(p.rho * p.body_force[i]);
+    return k;
+}
+
+template <typename T, bool EDDY, int MODE>
+nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, const T *f0, const T *f1, T *out,
+                    hipStream_t s) {
+    if (m->scatter == NSASM_SCATTER_PATCH) {
+        k_assemble_patch<T, EDDY, MODE><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
+            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->lconn, m->x, f0,
+            f1, kp, out);
+    } else {
+        const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
+        k_assemble_atomic<T, EDDY, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x,
+                                                                             f0, f1, kp, out);
+    }
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, "assembly kernel launch");
+}
+
+template <typename T, int MODE>
+nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, const void *f1, void *out,
+                 hipStream_t s) {
+    T *o = static_cast<T *>(out);
+    const int64_t n_out = 3 * m->n_nodes;
+    if (!(p.flags & NSASM_ACCUMULATE)) {
+        const int64_t blocks = std::min<int64_t>((n_out + kThreads - 1) / kThreads, 4096);
+        k_fill_zero<T><<<static_cast<unsigned>(blocks), kThreads, 0, s>>>(o, n_out);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return hip_fail(err, "fill kernel launch");
+    }
+    const KParams<T> kp = kernel_params<T>(p);
+    const T *a = static_cast<const T *>(f0), *b = static_cast<const T *>(f1);
+    if (p.smagorinsky_cs > 0.0) return launch<T, true, MODE>(m, kp, a, b, o, s);
+    return launch<T, false, MODE>(m, kp, a, b, o, s);
+}
+
+nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, const void *f0,
+                   const void *f1, void *out, void *stream, int mode) {
+    if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    NSASM_TRY(check_params(params));
+    if (prec != NSASM_FP64 && prec != NSASM_MIXED)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown precision %d", static_cast<int>(prec));
+    const char *n1 = (mode == kForward) ? "p" : "adjoint";
+    const char *no = (mode == kForward) ? "rhs" : "grad_u";
+    NSASM_TRY(check_device_ptr(f0, "u"));
+    NSASM_TRY(check_device_ptr(f1, n1));
+    NSASM_TRY(check_device_ptr(out, no));
+    const size_t es = (prec == NSASM_FP64) ? sizeof(double) : sizeof(float);
+    const size_t n3 = 3 * static_cast<size_t>(m->n_nodes) * es;
+    const size_t n1b = ((mode == kForward) ? 1 : 3) * static_cast<size_t>(m->n_nodes) * es;
+    if (overlaps(out, n3, f0, n3) || overlaps(out, n3, f1, n1b))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "%s overlaps an input", no);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nsasm_status st;
+    if (prec == NSASM_FP64)
+        st = (mode == kForward) ? run<double, kForward>(m, *params, f0, f1, out, s)
+                                : run<double, kVjp>(m, *params, f0, f1, out, s);
+    else
+        st = (mode == kForward) ? run<float, kForward>(m, *params, f0, f1, out, s)
+                                : run<float, kVjp>(m, *params, f0, f1, out, s);
+    if (st == NSASM_OK) clear_error();
+    return st;
+}
+
+}  // namespace
+}  // namespace nsasm
+
+extern "C" nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
+                                           nsasm_precision precision, const void *u, const void *p,
+                                           void *rhs, void *stream) {
+    return nsasm::entry(mesh, params, precision, u, p, rhs, stream, nsasm::kForward);
+}
+
+extern "C" nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *params,
+                                               nsasm_precision precision, const void *u,
+                                               const void *adjoint, void *grad_u, void *stream) {
+    return nsasm::entry(mesh, params, precision, u, adjoint, grad_u, stream, nsasm::kVjp);
+}

@@ -1,0 +1,607 @@
+// Mesh preprocessing: validation, Morton element order, first-touch node
+// renumbering, element patches; plus the user <-> mesh order helpers.
+//
+// The paper's kernels gather nodal values and scatter RHS entries through the
+// connectivity, and after removing intermediates those indirect accesses are
+// what remains (Sec. IV-C); their reuse happens in the shared cache.  On a
+// chip with eight L2 caches (one per XCD) that reuse depends on the order of
+// elements and on node numbering, so the mesh is reordered here once:
+//   1. elements sorted along a Morton curve of their centroids;
+//   2. nodes renumbered in order of first use by that element sequence, so the
+//      nodes of consecutive elements have nearby ids (coalesced gathers);
+//   3. the sequence cut into patches of E consecutive elements; for each patch
+//      the ascending list of its distinct nodes and one-byte local ids per
+//      element, so a workgroup can stage the patch's nodes through LDS.
+#include <algorithm>
+#include <climits>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace nsasm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kBadRange = 1u, kBadRepeat = 2u, kBadDet = 4u;
+constexpr int kBboxBlocks = 512;
+
+struct CreateFlags {
+    uint32_t bits;
+    int32_t first_bad;
+};
+
+__global__ __launch_bounds__(kThreads) void k_validate_ids(const int32_t *conn, int64_t ne, int64_t nn,
+                                                            CreateFlags *flags) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= ne) return;
+    const int4 c = reinterpret_cast<const int4 *>(conn)[e];
+    uint32_t bad = 0;
+    const int ids[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        if (ids[a] < 0 || ids[a] >= nn) bad |= kBadRange;
+    if (c.x == c.y || c.x == c.z || c.x == c.w || c.y == c.z || c.y == c.w || c.z == c.w) bad |= kBadRepeat;
+    if (bad) {
+        atomicOr(&flags->bits, bad);
+        atomicMin(&flags->first_bad, static_cast<int32_t>(e));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *x, int64_t nn, double *part) {
+    __shared__ double red[6][kThreads];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; k < nn;
+         k += static_cast<int64_t>(gridDim.x) * kThreads) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double v = x[3 * k + i];
+            lo[i] = fmin(lo[i], v);
+            hi[i] = fmax(hi[i], v);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        red[i][threadIdx.x] = lo[i];
+        red[3 + i][threadIdx.x] = hi[i];
+    }
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                red[i][threadIdx.x] = fmin(red[i][threadIdx.x], red[i][threadIdx.x + s]);
+                red[3 + i][threadIdx.x] = fmax(red[3 + i][threadIdx.x], red[3 + i][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *part, int nparts, double *box) {
+    __shared__ double red[6][kThreads];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double v = (i < 3) ? INFINITY : -INFINITY;
+        for (int k = threadIdx.x; k < nparts; k += kThreads) {
+            const double w = part[i * nparts + k];
+            v = (i < 3) ? fmin(v, w) : fmax(v, w);
+        }
+        red[i][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                red[i][threadIdx.x] = (i < 3) ? fmin(red[i][threadIdx.x], red[i][threadIdx.x + s])
+                                              : fmax(red[i][threadIdx.x], red[i][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) box[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Spread the low 21 bits of v to every third bit (3-D Morton interleave).
+__device__ inline uint64_t spread_bits3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Morton key of each element's centroid (63 bits) and the det J == 0 check.
+__global__ __launch_bounds__(kThreads) void k_element_keys(const double *x, const int32_t *conn,
+                                                            int64_t ne, const double *box,
+                                                            uint64_t *keys, int32_t *vals,
+                                                            CreateFlags *flags) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= ne) return;
+    const int4 c = reinterpret_cast<const int4 *>(conn)[e];
+    const int ids[4] = {c.x, c.y, c.z, c.w};
+    double xe[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xe[a][i] = x[3 * static_cast<int64_t>(ids[a]) + i];
+    double d[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d[k][i] = xe[k + 1][i] - xe[0][i];
+    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    if (det == 0.0 || !isfinite(det)) {
+        atomicOr(&flags->bits, kBadDet);
+        atomicMin(&flags->first_bad, static_cast<int32_t>(e));
+    }
+    const double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
+    const double scale = (ext > 0.0) ? 2097151.0 / ext : 0.0;
+    uint64_t key = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double cen = 0.25 * (xe[0][i] + xe[1][i] + xe[2][i] + xe[3][i]);
+        double q = (cen - box[i]) * scale;
+        q = fmin(fmax(q, 0.0), 2097151.0);
+        key |= spread_bits3(static_cast<uint64_t>(q)) << i;
+    }
+    keys[e] = key;
+    vals[e] = static_cast<int32_t>(e);
+}
+
+__global__ __launch_bounds__(kThreads) void k_iota(int32_t *v, int64_t n) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (k < n) v[k] = static_cast<int32_t>(k);
+}
+
+// first[n] = smallest (4 * position + local vertex) at which node n is used.
+__global__ __launch_bounds__(kThreads) void k_first_touch(const int32_t *conn, const int32_t *order,
+                                                           int64_t ne, uint32_t *first) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (s >= ne) return;
+    const int4 c = reinterpret_cast<const int4 *>(conn)[order[s]];
+    const uint32_t k = static_cast<uint32_t>(4 * s);
+    atomicMin(&first[c.x], k);
+    atomicMin(&first[c.y], k + 1);
+    atomicMin(&first[c.z], k + 2);
+    atomicMin(&first[c.w], k + 3);
+}
+
+__global__ __launch_bounds__(kThreads) void k_invert(const int32_t *iperm, int64_t n, int32_t *perm) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (k < n) perm[iperm[k]] = static_cast<int32_t>(k);
+}
+
+__global__ __launch_bounds__(kThreads) void k_remap_conn(const int32_t *conn, const int32_t *order,
+                                                          const int32_t *perm, int64_t ne, int4 *out) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (s >= ne) return;
+    const int4 c = reinterpret_cast<const int4 *>(conn)[order[s]];
+    out[s] = make_int4(perm[c.x], perm[c.y], perm[c.z], perm[c.w]);
+}
+
+// dst[k] = src[map[k]] for rows of ncomp elements.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_rows(const T *src, const int32_t *map, int64_t n,
+                                                           int ncomp, T *dst) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (k >= n * ncomp) return;
+    const int64_t row = k / ncomp;
+    const int c = static_cast<int>(k - row * ncomp);
+    dst[k] = src[static_cast<int64_t>(map[row]) * ncomp + c];
+}
+
+// Sort the 4E node ids of one patch in LDS (bitonic, padded with INT_MAX) and
+// mark the first of each run of equal ids.
+__device__ void patch_sorted_ids(const int4 *conn, int64_t ne, int64_t first_elem, int elems,
+                                 int32_t *ids /*LDS, 4*kMaxPatchElems*/) {
+    constexpr int kN = 4 * kMaxPatchElems;
+    const int32_t *flat = reinterpret_cast<const int32_t *>(conn);
+    for (int k = threadIdx.x; k < kN; k += kThreads) {
+        const int64_t s = first_elem + k / 4;
+        ids[k] = (k < 4 * elems && s < ne) ? flat[4 * first_elem + k] : INT_MAX;
+    }
+    __syncthreads();
+    for (int len = 2; len <= kN; len <<= 1) {
+        for (int j = len >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < kN; i += kThreads) {
+                const int partner = i ^ j;
+                if (partner > i) {
+                    const bool ascending = (i & len) == 0;
+                    const int32_t a = ids[i], b = ids[partner];
+                    if ((a > b) == ascending) {
+                        ids[i] = b;
+                        ids[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Pass 1: number of distinct nodes per patch.
+__global__ __launch_bounds__(kThreads) void k_patch_count(const int4 *conn, int64_t ne, int elems,
+                                                           uint32_t *count) {
+    __shared__ int32_t ids[4 * kMaxPatchElems];
+    __shared__ uint32_t lds4[4];
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
+    patch_sorted_ids(conn, ne, first, elems, ids);
+    uint32_t heads = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 4 * threadIdx.x + r;
+        heads += (ids[k] != INT_MAX && (k == 0 || ids[k] != ids[k - 1])) ? 1u : 0u;
+    }
+    uint32_t total;
+    (void)block_exclusive_scan_256(heads, lds4, &total);
+    if (threadIdx.x == 0) count[blockIdx.x] = total;
+}
+
+// Pass 2: write each patch's distinct nodes (ascending) and the one-byte local
+// ids of its elements.  Patches with more than kMaxPatchNodes nodes are
+// counted by pass 1 and rejected on the host before this runs.
+__global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64_t ne, int elems,
+                                                          const uint32_t *offset, int32_t *nodes,
+                                                          uint32_t *lconn) {
+    __shared__ int32_t ids[4 * kMaxPatchElems];
+    __shared__ int32_t uniq[4 * kMaxPatchElems];
+    __shared__ uint32_t lds4[4];
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
+    patch_sorted_ids(conn, ne, first, elems, ids);
+    uint32_t head[4], heads = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 4 * threadIdx.x + r;
+        head[r] = (ids[k] != INT_MAX && (k == 0 || ids[k] != ids[k - 1])) ? 1u : 0u;
+        heads += head[r];
+    }
+    uint32_t total;
+    uint32_t pos = block_exclusive_scan_256(heads, lds4, &total);
+    const uint32_t base = offset[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (head[r]) {
+            const int32_t id = ids[4 * threadIdx.x + r];
+            uniq[pos] = id;
+            nodes[base + pos] = id;
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const int64_t s = first + threadIdx.x;
+    if (threadIdx.x < elems && s < ne) {
+        const int4 c = conn[s];
+        const int32_t v[4] = {c.x, c.y, c.z, c.w};
+        uint32_t packed = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            int lo = 0, hi = static_cast<int>(total) - 1;
+            while (lo < hi) {  // first index with uniq[idx] >= v[a]
+                const int mid = (lo + hi) >> 1;
+                if (uniq[mid] < v[a]) lo = mid + 1;
+                else hi = mid;
+            }
+            packed |= static_cast<uint32_t>(lo & 0xff) << (8 * a);
+        }
+        lconn[s] = packed;
+    }
+}
+
+inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
+
+nsasm_status check_launch(const char *what) {
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, what);
+}
+
+void free_mesh(nsasm_mesh *m) {
+    if (!m) return;
+    device_free(m->perm);
+    device_free(m->iperm);
+    device_free(m->user_elem);
+    device_free(m->conn);
+    device_free(m->x);
+    device_free(m->patch_off);
+    device_free(m->patch_nodes);
+    device_free(m->lconn);
+    delete m;
+}
+
+nsasm_status read_flags(const CreateFlags *d_flags, hipStream_t stream, CreateFlags *h) {
+    NSASM_HIP(hipMemcpyAsync(h, d_flags, sizeof(CreateFlags), hipMemcpyDeviceToHost, stream));
+    NSASM_HIP(hipStreamSynchronize(stream));
+    return NSASM_OK;
+}
+
+// Build patches of `elems` consecutive mesh-order elements.  Returns
+// UNSUPPORTED (without touching m) when a patch has too many distinct nodes.
+nsasm_status build_patches(nsasm_mesh *m, int elems, hipStream_t stream) {
+    const int64_t np = (m->n_elems + elems - 1) / elems;
+    if (np >= INT_MAX) return fail(NSASM_ERR_UNSUPPORTED, "too many patches");
+    uint32_t *count = nullptr;
+    NSASM_TRY(device_alloc(&count, static_cast<size_t>(np + 1), "patch counts"));
+    k_patch_count<<<static_cast<unsigned>(np), kThreads, 0, stream>>>(m->conn, m->n_elems, elems, count);
+    nsasm_status st = check_launch("k_patch_count");
+    std::vector<uint32_t> host(static_cast<size_t>(np));
+    if (st == NSASM_OK) {
+        hipError_t err = hipMemcpyAsync(host.data(), count, sizeof(uint32_t) * np, hipMemcpyDeviceToHost, stream);
+        if (err == hipSuccess) err = hipStreamSynchronize(stream);
+        if (err != hipSuccess) st = hip_fail(err, "patch counts");
+    }
+    uint32_t max_nodes = 0;
+    if (st == NSASM_OK) max_nodes = *std::max_element(host.begin(), host.end());
+    if (st == NSASM_OK && max_nodes > static_cast<uint32_t>(kMaxPatchNodes))
+        st = fail(NSASM_ERR_UNSUPPORTED,
+                  "a patch of %d elements touches %u distinct nodes (limit %d); use a smaller "
+                  "patch, renumbering, or atomic scatter",
+                  elems, max_nodes, kMaxPatchNodes);
+    uint32_t total = 0;
+    if (st == NSASM_OK) st = exclusive_scan_u32(count, count, np, &total, stream);
+    if (st == NSASM_OK) {
+        hipError_t err = hipMemcpyAsync(count + np, &total, sizeof(uint32_t), hipMemcpyHostToDevice, stream);
+        if (err != hipSuccess) st = hip_fail(err, "patch offsets");
+    }
+    if (st == NSASM_OK) st = device_alloc(&m->patch_nodes, total, "patch nodes");
+    if (st == NSASM_OK) st = device_alloc(&m->lconn, static_cast<size_t>(m->n_elems), "patch local ids");
+    if (st == NSASM_OK) {
+        k_patch_fill<<<static_cast<unsigned>(np), kThreads, 0, stream>>>(
+            m->conn, m->n_elems, elems, count, m->patch_nodes, m->lconn);
+        st = check_launch("k_patch_fill");
+    }
+    if (st == NSASM_OK) {
+        hipError_t err = hipStreamSynchronize(stream);
+        if (err != hipSuccess) st = hip_fail(err, "patch build");
+    }
+    if (st != NSASM_OK) {
+        device_free(count);
+        device_free(m->patch_nodes);
+        device_free(m->lconn);
+        m->patch_nodes = nullptr;
+        m->lconn = nullptr;
+        return st;
+    }
+    m->patch_off = reinterpret_cast<int32_t *>(count);
+    m->n_patches = static_cast<int32_t>(np);
+    m->patch_elems = elems;
+    m->max_patch_nodes = static_cast<int32_t>(max_nodes);
+    m->patch_node_refs = total;
+    return NSASM_OK;
+}
+
+nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64_t ne,
+                    const nsasm_mesh_options &opt, hipStream_t stream, nsasm_mesh *m) {
+    m->n_nodes = nn;
+    m->n_elems = ne;
+    NSASM_HIP(hipGetDevice(&m->device));
+
+    CreateFlags *d_flags = nullptr;
+    NSASM_TRY(device_alloc(&d_flags, 1, "create flags"));
+    struct Scratch {
+        CreateFlags *flags;
+        double *box = nullptr;
+        uint64_t *keys = nullptr;
+        uint32_t *first = nullptr;
+        ~Scratch() {
+            device_free(flags);
+            device_free(box);
+            device_free(keys);
+            device_free(first);
+        }
+    } scratch{d_flags};
+
+    const CreateFlags init{0u, INT_MAX};
+    NSASM_HIP(hipMemcpyAsync(d_flags, &init, sizeof init, hipMemcpyHostToDevice, stream));
+    k_validate_ids<<<blocks_for(ne), kThreads, 0, stream>>>(conn, ne, nn, d_flags);
+    NSASM_TRY(check_launch("k_validate_ids"));
+    CreateFlags h{};
+    NSASM_TRY(read_flags(d_flags, stream, &h));
+    if (h.bits & kBadRange)
+        return fail(NSASM_ERR_BAD_CONNECTIVITY, "node id out of [0, %lld) (first bad element %d)",
+                    static_cast<long long>(nn), h.first_bad);
+    if (h.bits & kBadRepeat)
+        return fail(NSASM_ERR_BAD_CONNECTIVITY, "repeated node in a tetrahedron (first bad element %d)",
+                    h.first_bad);
+
+    NSASM_TRY(device_alloc(&scratch.box, 6 + 6 * kBboxBlocks, "bounding box"));
+    k_bbox_partial<<<kBboxBlocks, kThreads, 0, stream>>>(coords, nn, scratch.box + 6);
+    NSASM_TRY(check_launch("k_bbox_partial"));
+    k_bbox_final<<<1, kThreads, 0, stream>>>(scratch.box + 6, kBboxBlocks, scratch.box);
+    NSASM_TRY(check_launch("k_bbox_final"));
+
+    NSASM_TRY(device_alloc(&scratch.keys, static_cast<size_t>(ne), "element keys"));
+    NSASM_TRY(device_alloc(&m->user_elem, static_cast<size_t>(ne), "element order"));
+    k_element_keys<<<blocks_for(ne), kThreads, 0, stream>>>(coords, conn, ne, scratch.box, scratch.keys,
+                                                             m->user_elem, d_flags);
+    NSASM_TRY(check_launch("k_element_keys"));
+    NSASM_TRY(read_flags(d_flags, stream, &h));
+    if (h.bits & kBadDet)
+        return fail(NSASM_ERR_DEGENERATE_ELEMENT, "element %d has det J == 0 or a non-finite vertex",
+                    h.first_bad);
+
+    NSASM_TRY(device_alloc(&m->perm, static_cast<size_t>(nn), "node permutation"));
+    NSASM_TRY(device_alloc(&m->iperm, static_cast<size_t>(nn), "inverse node permutation"));
+    if (opt.renumber) {
+        NSASM_TRY(radix_sort_pairs_u64(scratch.keys, m->user_elem, ne, 63, stream));
+        NSASM_TRY(device_alloc(&scratch.first, static_cast<size_t>(nn), "first touch"));
+        NSASM_HIP(hipMemsetAsync(scratch.first, 0xff, sizeof(uint32_t) * nn, stream));
+        k_first_touch<<<blocks_for(ne), kThreads, 0, stream>>>(conn, m->user_elem, ne, scratch.first);
+        NSASM_TRY(check_launch("k_first_touch"));
+        k_iota<<<blocks_for(nn), kThreads, 0, stream>>>(m->iperm, nn);
+        NSASM_TRY(check_launch("k_iota"));
+        // stable: nodes used by no element keep their relative order at the end
+        NSASM_TRY(radix_sort_pairs_u32(scratch.first, m->iperm, nn, 32, stream));
+        k_invert<<<blocks_for(nn), kThreads, 0, stream>>>(m->iperm, nn, m->perm);
+        NSASM_TRY(check_launch("k_invert"));
+        m->renumbered = 1;
+    } else {
+        k_iota<<<blocks_for(ne), kThreads, 0, stream>>>(m->user_elem, ne);
+        NSASM_TRY(check_launch("k_iota"));
+        k_iota<<<blocks_for(nn), kThreads, 0, stream>>>(m->iperm, nn);
+        NSASM_TRY(check_launch("k_iota"));
+        k_iota<<<blocks_for(nn), kThreads, 0, stream>>>(m->perm, nn);
+        NSASM_TRY(check_launch("k_iota"));
+        m->renumbered = 0;
+    }
+
+    NSASM_TRY(device_alloc(&m->conn, static_cast<size_t>(ne), "mesh connectivity"));
+    k_remap_conn<<<blocks_for(ne), kThreads, 0, stream>>>(conn, m->user_elem, m->perm, ne, m->conn);
+    NSASM_TRY(check_launch("k_remap_conn"));
+    NSASM_TRY(device_alloc(&m->x, static_cast<size_t>(3 * nn), "mesh coordinates"));
+    k_gather_rows<double><<<blocks_for(3 * nn), kThreads, 0, stream>>>(coords, m->iperm, nn, 3, m->x);
+    NSASM_TRY(check_launch("k_gather_rows"));
+
+    m->scatter = NSASM_SCATTER_ATOMIC;
+    if (opt.scatter != NSASM_SCATTER_ATOMIC) {
+        const int elems = opt.patch_elems > 0 ? opt.patch_elems : kMaxPatchElems;
+        nsasm_status st = build_patches(m, elems, stream);
+        if (st == NSASM_OK) {
+            m->scatter = NSASM_SCATTER_PATCH;
+        } else if (!(st == NSASM_ERR_UNSUPPORTED && opt.scatter == NSASM_SCATTER_AUTO)) {
+            return st;
+        }
+    }
+    NSASM_HIP(hipStreamSynchronize(stream));
+    clear_error();
+    return NSASM_OK;
+}
+
+template <typename T>
+nsasm_status reorder(const nsasm_mesh *m, int32_t ncomp, const void *src, void *dst, bool to_mesh,
+                     hipStream_t stream) {
+    const int32_t *map = to_mesh ? m->iperm : m->perm;
+    k_gather_rows<T><<<blocks_for(m->n_nodes * ncomp), kThreads, 0, stream>>>(
+        static_cast<const T *>(src), map, m->n_nodes, ncomp, static_cast<T *>(dst));
+    return check_launch("k_gather_rows");
+}
+
+nsasm_status reorder_entry(const nsasm_mesh *m, int32_t ncomp, nsasm_precision prec, const void *src,
+                           void *dst, void *stream, bool to_mesh) {
+    if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    if (ncomp < 1 || ncomp > 16) return fail(NSASM_ERR_INVALID_ARGUMENT, "ncomp must be in 1..16");
+    if (prec != NSASM_FP64 && prec != NSASM_MIXED)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown precision %d", static_cast<int>(prec));
+    NSASM_TRY(check_device_ptr(src, to_mesh ? "user" : "mesh_ordered"));
+    NSASM_TRY(check_device_ptr(dst, to_mesh ? "mesh_ordered" : "user"));
+    if (src == dst) return fail(NSASM_ERR_INVALID_ARGUMENT, "source and destination must differ");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    nsasm_status st = (prec == NSASM_FP64) ? reorder<double>(m, ncomp, src, dst, to_mesh, s)
+                                           : reorder<float>(m, ncomp, src, dst, to_mesh, s);
+    if (st == NSASM_OK) clear_error();
+    return st;
+}
+
+}  // namespace
+}  // namespace nsasm
+
+extern "C" nsasm_status nsasm_mesh_create(const double *coords, int64_t n_nodes, const int32_t *conn,
+                                          int64_t n_elems, const nsasm_mesh_options *opts, void *stream,
+                                          nsasm_mesh **out) {
+    using namespace nsasm;
+    if (!out) return fail(NSASM_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!coords) return fail(NSASM_ERR_INVALID_ARGUMENT, "coords is NULL");
+    if (!conn) return fail(NSASM_ERR_INVALID_ARGUMENT, "conn is NULL");
+    if (n_nodes <= 0 || n_nodes >= (int64_t(1) << 31))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "n_nodes must be in [1, 2^31)");
+    if (n_elems <= 0 || n_elems >= (int64_t(1) << 29))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "n_elems must be in [1, 2^29)");
+    nsasm_mesh_options opt{1, NSASM_SCATTER_AUTO, 0, 0};
+    if (opts) opt = *opts;
+    if (opt.renumber != 0 && opt.renumber != 1)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "renumber must be 0 or 1");
+    if (opt.scatter < NSASM_SCATTER_AUTO || opt.scatter > NSASM_SCATTER_PATCH)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown scatter mode %d", opt.scatter);
+    if (opt.patch_elems != 0 &&
+        (opt.patch_elems < 32 || opt.patch_elems > kMaxPatchElems || opt.patch_elems % 32 != 0))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "patch_elems must be 0 or a multiple of 32 in [32, 256]");
+    if (opt.reserved != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "reserved option must be 0");
+    NSASM_TRY(check_device_ptr(coords, "coords"));
+    NSASM_TRY(check_device_ptr(conn, "conn"));
+
+    nsasm_mesh *m = new (std::nothrow) nsasm_mesh();
+    if (!m) return fail(NSASM_ERR_OUT_OF_MEMORY, "host allocation of the mesh handle failed");
+    nsasm_status st = create(coords, n_nodes, conn, n_elems, opt, static_cast<hipStream_t>(stream), m);
+    if (st != NSASM_OK) {
+        std::string msg = nsasm_last_error();
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        free_mesh(m);
+        fail(st, "%s", msg.c_str());
+        return st;
+    }
+    *out = m;
+    return NSASM_OK;
+}
+
+extern "C" nsasm_status nsasm_mesh_destroy(nsasm_mesh *mesh) {
+    if (!mesh) return NSASM_OK;
+    hipError_t err = hipDeviceSynchronize();
+    nsasm::free_mesh(mesh);
+    if (err != hipSuccess) return nsasm::hip_fail(err, "hipDeviceSynchronize in nsasm_mesh_destroy");
+    nsasm::clear_error();
+    return NSASM_OK;
+}
+
+extern "C" nsasm_status nsasm_mesh_info(const nsasm_mesh *mesh, nsasm_mesh_info_t *info) {
+    using namespace nsasm;
+    if (!mesh) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    if (!info) return fail(NSASM_ERR_INVALID_ARGUMENT, "info is NULL");
+    *info = nsasm_mesh_info_t{};
+    info->n_nodes = mesh->n_nodes;
+    info->n_elems = mesh->n_elems;
+    info->scatter = mesh->scatter;
+    info->renumbered = mesh->renumbered;
+    info->n_patches = mesh->n_patches;
+    info->patch_elems = mesh->patch_elems;
+    info->max_patch_nodes = mesh->max_patch_nodes;
+    info->patch_node_refs = mesh->patch_node_refs;
+    clear_error();
+    return NSASM_OK;
+}
+
+extern "C" nsasm_status nsasm_mesh_permutation(const nsasm_mesh *mesh, int32_t *mesh_id_of_user,
+                                               void *stream) {
+    using namespace nsasm;
+    if (!mesh) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    NSASM_TRY(check_device_ptr(mesh_id_of_user, "mesh_id_of_user"));
+    NSASM_HIP(hipMemcpyAsync(mesh_id_of_user, mesh->perm, sizeof(int32_t) * mesh->n_nodes,
+                             hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+    clear_error();
+    return NSASM_OK;
+}
+
+extern "C" nsasm_status nsasm_mesh_connectivity(const nsasm_mesh *mesh, int32_t *conn_mesh,
+                                                int32_t *user_elem, void *stream) {
+    using namespace nsasm;
+    if (!mesh) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (conn_mesh) {
+        NSASM_TRY(check_device_ptr(conn_mesh, "conn_mesh"));
+        NSASM_HIP(hipMemcpyAsync(conn_mesh, mesh->conn, sizeof(int4) * mesh->n_elems,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    if (user_elem) {
+        NSASM_TRY(check_device_ptr(user_elem, "user_elem"));
+        NSASM_HIP(hipMemcpyAsync(user_elem, mesh->user_elem, sizeof(int32_t) * mesh->n_elems,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    clear_error();
+    return NSASM_OK;
+}
+
+extern "C" nsasm_status nsasm_to_mesh_order(const nsasm_mesh *mesh, int32_t ncomp,
+                                            nsasm_precision precision, const void *user,
+                                            void *mesh_ordered, void *stream) {
+    return nsasm::reorder_entry(mesh, ncomp, precision, user, mesh_ordered, stream, true);
+}
+
+extern "C" nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t ncomp,
+                                              nsasm_precision precision, const void *mesh_ordered,
+                                              void *user, void *stream) {
+    return nsasm::reorder_entry(mesh, ncomp, precision, mesh_ordered, user, stream, false);
+}
