@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--scatter", default="auto", choices=["auto", "atomic", "patch"])
     ap.add_argument("--patch-elems", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a plain device copy of 1 GiB (HBM bandwidth and counter calibration)")
     return ap.parse_args()
 
 
@@ -202,6 +204,17 @@ def main():
         "forms": forms,
         "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms},
     }
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        cp = kernel_ms(lambda: b.copy_(a), 5)
+        result["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "mean_ms": cp[0],
+                                      "GBs_read_plus_write": 2 * nbytes / (cp[0] * 1e-3) / 1e9}
+        log(f"[bench] copy of 1 GiB: {cp[0]:.3f} ms, {2 * nbytes / (cp[0] * 1e-3) / 1e9:.0f} GB/s (read+write)")
+        del a, b
 
     if not args.no_cpu_baseline:
         import oracle

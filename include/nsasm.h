@@ -69,9 +69,15 @@ typedef enum {
 typedef enum {
     NSASM_SCATTER_AUTO = 0,   /* PATCH when the mesh allows it, else ATOMIC */
     NSASM_SCATTER_ATOMIC = 1, /* one thread per element, 12 global atomic adds */
-    NSASM_SCATTER_PATCH = 2   /* element patches staged through LDS: nodes gathered
-                                 once per patch, element sums reduced in LDS, one
-                                 global atomic add per patch node and component */
+    NSASM_SCATTER_PATCH = 2,  /* element patches staged through LDS: nodes gathered
+                                 once per patch, element contributions summed per
+                                 node in LDS, one global atomic add per patch node
+                                 and component */
+    NSASM_SCATTER_PATCH_GATHER = 3 /* as PATCH, but each patch writes its per-node sums
+                                 to a partial-sum buffer owned by the mesh and a
+                                 second kernel sums them per node in a fixed order:
+                                 no atomics, bitwise reproducible; assembly calls
+                                 on one mesh must not overlap in time */
 } nsasm_scatter;
 
 /* Set in nsasm_params.flags: add into the output instead of overwriting it. */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libnsasm.so")
 
 FP64 = 0
 MIXED = 1
-_SCATTER = {"auto": 0, "atomic": 1, "patch": 2}
+_SCATTER = {"auto": 0, "atomic": 1, "patch": 2, "patch_gather": 3}
 _SCATTER_NAMES = {v: k for k, v in _SCATTER.items()}
 ACCUMULATE = 1
 

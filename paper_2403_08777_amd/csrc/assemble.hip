@@ -32,8 +32,12 @@
 //   ATOMIC: one thread per element, 12 global atomic adds.
 //   PATCH:  one workgroup per patch of <= 256 consecutive (Morton-ordered)
 //           elements; the patch's <= 256 distinct nodes are loaded once into
-//           LDS, element contributions are summed with LDS atomics, and each
-//           patch node gets one global atomic add per component.
+//           LDS, element contributions are summed per node in LDS (slot runs,
+//           no LDS atomics), and each patch node gets one global atomic add
+//           per component.
+//   PATCH_GATHER: as PATCH, but the per-patch node sums go to a partial-sum
+//           buffer and a node-parallel kernel adds them in patch order: no
+//           atomics anywhere, bitwise reproducible, no zero-fill.
 #include <algorithm>
 #include <cmath>
 
@@ -60,12 +64,6 @@ __device__ inline void global_add(double *p, double v) {
 }
 __device__ inline void global_add(float *p, float v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void lds_add(double *p, double v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ inline void lds_add(float *p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ inline double cube_root(double v) { return cbrt(v); }
@@ -283,43 +281,63 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
         for (int i = 0; i < 3; ++i) global_add(&out[3 * ids[a] + i], r[a][i]);
 }
 
-// One workgroup per patch (see the file header).
-template <typename T, bool EDDY, int MODE>
+// One workgroup per patch (see the file header).  LDS holds the patch's
+// node data while elements gather it, then (reusing the same bytes) the
+// element contributions at their precomputed slots: slots are sorted by node,
+// so each node's contributions form one contiguous run that a single thread
+// sums in a fixed order.  GATHER = false adds each node sum to `out` with a
+// global atomic; GATHER = true stores it to the node-major partial-sum buffer
+// (position ref_slot of the patch reference), for k_gather_partials.
+template <typename T, bool EDDY, int MODE, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_assemble_patch(
-    int64_t ne, int32_t n_patches, int32_t patch_elems, const int32_t *__restrict__ patch_off,
-    const int32_t *__restrict__ patch_nodes, const uint32_t *__restrict__ lconn,
-    const double *__restrict__ x, const T *__restrict__ f0, const T *__restrict__ f1, KParams<T> P,
-    T *__restrict__ out) {
+    int64_t ne, int64_t np, int32_t patch_elems, const int32_t *__restrict__ patch_off,
+    const int32_t *__restrict__ patch_nodes, const int32_t *__restrict__ patch_node_start,
+    const int32_t *__restrict__ ref_slot, const ushort4 *__restrict__ elem_pos, const double *__restrict__ x,
+    const T *__restrict__ f0, const T *__restrict__ f1, KParams<T> P, T *__restrict__ out) {
     constexpr int kF1 = (MODE == kForward) ? 1 : 3;
-    __shared__ double sx[3][kMaxPatchNodes];
-    __shared__ T su[3][kMaxPatchNodes];
-    __shared__ T s1[kF1][kMaxPatchNodes];
-    __shared__ T sacc[3][kMaxPatchNodes];
+    constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
+    constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + (3 + kF1) * kN * sizeof(T);
+    constexpr size_t kSlotBytes = 3 * kS * sizeof(T);
+    __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
+    __shared__ uint8_t node_of_slot[kS];
+    double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
+    T(*su)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));
+    T(*s1)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double) + 3 * kN * sizeof(T));
+    T(*sval)[kS] = reinterpret_cast<T(*)[kS]>(smem);
 
     const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
-    if (patch >= n_patches) return;
+    if (patch >= np) return;
     const int t = threadIdx.x;
     const int32_t beg = patch_off[patch];
     const int32_t cnt = patch_off[patch + 1] - beg;
+    const int64_t first = patch * static_cast<int64_t>(patch_elems);
+    const int nel = static_cast<int>(min<int64_t>(patch_elems, ne - first));
+    ushort4 pos = make_ushort4(0, 0, 0, 0);
+    if (t < nel) pos = elem_pos[first + t];
     int64_t node = 0;
+    int32_t slot = 0, s_beg = 0, s_end = 0;
     if (t < cnt) {
         node = patch_nodes[beg + t];
+        s_beg = patch_node_start[beg + t];
+        s_end = (t + 1 < cnt) ? patch_node_start[beg + t + 1] : 4 * nel;
+        if (GATHER) slot = ref_slot[beg + t];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             sx[i][t] = x[3 * node + i];
             su[i][t] = f0[3 * node + i];
-            sacc[i][t] = T(0);
         }
 #pragma unroll
         for (int i = 0; i < kF1; ++i) s1[i][t] = f1[kF1 * node + i];
+        for (int k = s_beg; k < s_end; ++k) node_of_slot[k] = static_cast<uint8_t>(t);
     }
     __syncthreads();
 
-    const int64_t e = static_cast<int64_t>(patch) * patch_elems + t;
-    if (t < patch_elems && e < ne) {
-        const uint32_t lc = lconn[e];
-        const int la[4] = {static_cast<int>(lc & 0xff), static_cast<int>((lc >> 8) & 0xff),
-                           static_cast<int>((lc >> 16) & 0xff), static_cast<int>(lc >> 24)};
+    T r[4][3];
+    const int sl[4] = {pos.x, pos.y, pos.z, pos.w};
+    if (t < nel) {
+        int la[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) la[a] = node_of_slot[sl[a]];
         double xe[4][3];
         T ue[4][3];
 #pragma unroll
@@ -333,7 +351,6 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
         tet_geometry(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
-        T r[4][3];
         if (MODE == kForward) {
             T pe[4];
 #pragma unroll
@@ -347,16 +364,45 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
                 for (int i = 0; i < 3; ++i) le[a][i] = s1[i][la[a]];
             element_vjp<T, EDDY>(gN, vol, ue, le, P, r);
         }
+    }
+    __syncthreads();  // node data is dead from here on; its bytes become slots
+    if (t < nel) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) lds_add(&sacc[i][la[a]], r[a][i]);
+            for (int i = 0; i < 3; ++i) sval[i][sl[a]] = r[a][i];
     }
     __syncthreads();
     if (t < cnt) {
+        T acc[3] = {T(0), T(0), T(0)};
+        for (int k = s_beg; k < s_end; ++k)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) global_add(&out[3 * node + i], sacc[i][t]);
+            for (int i = 0; i < 3; ++i) acc[i] += sval[i][k];
+        if (GATHER) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) out[3 * static_cast<int64_t>(slot) + i] = acc[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) global_add(&out[3 * node + i], acc[i]);
+        }
     }
+}
+
+// out[n] (+)= sum of node n's patch partial sums, which are stored
+// contiguously (node-major, patch order) at [ref_off[n], ref_off[n+1]).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_partials(int64_t nn, const int32_t *__restrict__ ref_off,
+                                                               const T *__restrict__ partial, T *__restrict__ out,
+                                                               int accumulate) {
+    const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (n >= nn) return;
+    T acc[3] = {T(0), T(0), T(0)};
+    const int64_t kb = ref_off[n], ke = ref_off[n + 1];
+    for (int64_t k = kb; k < ke; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] += partial[3 * k + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[3 * n + i] = accumulate ? out[3 * n + i] + acc[i] : acc[i];
 }
 
 // ---------------------------------------------------------- host side
@@ -392,11 +438,21 @@ KParams<T> kernel_params(const nsasm_params &p) {
 
 template <typename T, bool EDDY, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, const T *f0, const T *f1, T *out,
-                    hipStream_t s) {
-    if (m->scatter == NSASM_SCATTER_PATCH) {
-        k_assemble_patch<T, EDDY, MODE><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
-            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->lconn, m->x, f0,
-            f1, kp, out);
+                    bool accumulate, hipStream_t s) {
+    if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
+        T *partial = reinterpret_cast<T *>(m->partial);
+        k_assemble_patch<T, EDDY, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
+            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
+            m->ref_slot, m->elem_pos, m->x, f0, f1, kp, partial);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
+        const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
+        k_gather_partials<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial, out,
+                                                                  accumulate ? 1 : 0);
+    } else if (m->scatter == NSASM_SCATTER_PATCH) {
+        k_assemble_patch<T, EDDY, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
+            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
+            m->ref_slot, m->elem_pos, m->x, f0, f1, kp, out);
     } else {
         const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
         k_assemble_atomic<T, EDDY, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x,
@@ -411,7 +467,9 @@ nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, con
                  hipStream_t s) {
     T *o = static_cast<T *>(out);
     const int64_t n_out = 3 * m->n_nodes;
-    if (!(p.flags & NSASM_ACCUMULATE)) {
+    const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
+    // the gather kernel writes every node, so it needs no zero-fill
+    if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER) {
         const int64_t blocks = std::min<int64_t>((n_out + kThreads - 1) / kThreads, 4096);
         k_fill_zero<T><<<static_cast<unsigned>(blocks), kThreads, 0, s>>>(o, n_out);
         hipError_t err = hipGetLastError();
@@ -419,8 +477,8 @@ nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, con
     }
     const KParams<T> kp = kernel_params<T>(p);
     const T *a = static_cast<const T *>(f0), *b = static_cast<const T *>(f1);
-    if (p.smagorinsky_cs > 0.0) return launch<T, true, MODE>(m, kp, a, b, o, s);
-    return launch<T, false, MODE>(m, kp, a, b, o, s);
+    if (p.smagorinsky_cs > 0.0) return launch<T, true, MODE>(m, kp, a, b, o, accumulate, s);
+    return launch<T, false, MODE>(m, kp, a, b, o, accumulate, s);
 }
 
 nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, const void *f0,

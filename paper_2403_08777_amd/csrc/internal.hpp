@@ -70,8 +70,14 @@ struct nsasm_mesh {
     int32_t max_patch_nodes = 0;
     int64_t patch_node_refs = 0;
     int32_t *patch_off = nullptr;   // [n_patches + 1] offsets into patch_nodes
-    int32_t *patch_nodes = nullptr; // distinct mesh node ids of each patch, ascending
-    uint32_t *lconn = nullptr;      // [n_elems] 4 one-byte patch-local node ids
+    int32_t *patch_nodes = nullptr;        // distinct mesh node ids of each patch, ascending
+    int32_t *patch_node_start = nullptr;   // first slot of each patch node (same indexing, +1 padding)
+    ushort4 *elem_pos = nullptr;           // [n_elems] slot of each (element, vertex)
+
+    // deterministic gather of per-patch partial sums (scatter == PATCH_GATHER)
+    int32_t *node_ref_off = nullptr;  // [n_nodes + 1] each node's run in the partial buffer
+    int32_t *ref_slot = nullptr;      // [patch_node_refs] node-major position of each patch reference
+    double *partial = nullptr;        // [3 * patch_node_refs] partial sums (float or double)
 };
 
 namespace nsasm {

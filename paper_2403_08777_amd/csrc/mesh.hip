@@ -196,27 +196,19 @@ __global__ __launch_bounds__(kThreads) void k_gather_rows(const T *src, const in
     dst[k] = src[static_cast<int64_t>(map[row]) * ncomp + c];
 }
 
-// Sort the 4E node ids of one patch in LDS (bitonic, padded with INT_MAX) and
-// mark the first of each run of equal ids.
-__device__ void patch_sorted_ids(const int4 *conn, int64_t ne, int64_t first_elem, int elems,
-                                 int32_t *ids /*LDS, 4*kMaxPatchElems*/) {
-    constexpr int kN = 4 * kMaxPatchElems;
-    const int32_t *flat = reinterpret_cast<const int32_t *>(conn);
-    for (int k = threadIdx.x; k < kN; k += kThreads) {
-        const int64_t s = first_elem + k / 4;
-        ids[k] = (k < 4 * elems && s < ne) ? flat[4 * first_elem + k] : INT_MAX;
-    }
-    __syncthreads();
+// Bitonic sort of kN keys in LDS (kN a power of two), 256 threads.
+template <typename K, int kN>
+__device__ void lds_bitonic_sort(K *keys) {
     for (int len = 2; len <= kN; len <<= 1) {
         for (int j = len >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < kN; i += kThreads) {
                 const int partner = i ^ j;
                 if (partner > i) {
                     const bool ascending = (i & len) == 0;
-                    const int32_t a = ids[i], b = ids[partner];
+                    const K a = keys[i], b = keys[partner];
                     if ((a > b) == ascending) {
-                        ids[i] = b;
-                        ids[partner] = a;
+                        keys[i] = b;
+                        keys[partner] = a;
                     }
                 }
             }
@@ -225,72 +217,89 @@ __device__ void patch_sorted_ids(const int4 *conn, int64_t ne, int64_t first_ele
     }
 }
 
+constexpr int kPatchSlots = 4 * kMaxPatchElems;   // 1024 (element, vertex) pairs
+constexpr uint64_t kNoKey = ~0ull;
+
+// Keys (node id << 10 | slot) of one patch, slot = 4 * local element + vertex;
+// padded with kNoKey.  Sorted, they list each node's slots contiguously, in
+// slot order.
+__device__ void patch_sorted_pairs(const int4 *conn, int64_t ne, int64_t first_elem, int elems,
+                                   uint64_t *keys /*LDS, kPatchSlots*/) {
+    const int32_t *flat = reinterpret_cast<const int32_t *>(conn);
+    const int nslots = 4 * static_cast<int>(min<int64_t>(elems, ne - first_elem));
+    for (int k = threadIdx.x; k < kPatchSlots; k += kThreads)
+        keys[k] = (k < nslots) ? ((static_cast<uint64_t>(flat[4 * first_elem + k]) << 10) | static_cast<uint64_t>(k))
+                               : kNoKey;
+    __syncthreads();
+    lds_bitonic_sort<uint64_t, kPatchSlots>(keys);
+}
+
+__device__ inline bool run_head(const uint64_t *keys, int k) {
+    return keys[k] != kNoKey && (k == 0 || (keys[k] >> 10) != (keys[k - 1] >> 10));
+}
+
 // Pass 1: number of distinct nodes per patch.
 __global__ __launch_bounds__(kThreads) void k_patch_count(const int4 *conn, int64_t ne, int elems,
                                                            uint32_t *count) {
-    __shared__ int32_t ids[4 * kMaxPatchElems];
+    __shared__ uint64_t keys[kPatchSlots];
     __shared__ uint32_t lds4[4];
     const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
-    patch_sorted_ids(conn, ne, first, elems, ids);
+    patch_sorted_pairs(conn, ne, first, elems, keys);
     uint32_t heads = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int k = 4 * threadIdx.x + r;
-        heads += (ids[k] != INT_MAX && (k == 0 || ids[k] != ids[k - 1])) ? 1u : 0u;
-    }
+    for (int r = 0; r < 4; ++r) heads += run_head(keys, 4 * threadIdx.x + r) ? 1u : 0u;
     uint32_t total;
     (void)block_exclusive_scan_256(heads, lds4, &total);
     if (threadIdx.x == 0) count[blockIdx.x] = total;
 }
 
-// Pass 2: write each patch's distinct nodes (ascending) and the one-byte local
-// ids of its elements.  Patches with more than kMaxPatchNodes nodes are
-// counted by pass 1 and rejected on the host before this runs.
+// Pass 2: for each patch write its distinct nodes (ascending), the start of
+// each node's run of slots in node-sorted order, and for every element the
+// sorted positions of its four (element, vertex) slots.  An assembly
+// workgroup stores element contributions at those positions and then sums
+// each node's run: a deterministic in-LDS reduction without atomics.
+// Patches with more than kMaxPatchNodes nodes are rejected (from pass 1) on
+// the host before this runs.
 __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64_t ne, int elems,
                                                           const uint32_t *offset, int32_t *nodes,
-                                                          uint32_t *lconn) {
-    __shared__ int32_t ids[4 * kMaxPatchElems];
-    __shared__ int32_t uniq[4 * kMaxPatchElems];
+                                                          int32_t *node_start, ushort4 *elem_pos) {
+    __shared__ uint64_t keys[kPatchSlots];
+    __shared__ uint16_t pos_of_slot[kPatchSlots];
     __shared__ uint32_t lds4[4];
     const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
-    patch_sorted_ids(conn, ne, first, elems, ids);
-    uint32_t head[4], heads = 0;
+    patch_sorted_pairs(conn, ne, first, elems, keys);
+    bool head[4];
+    uint32_t heads = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int k = 4 * threadIdx.x + r;
-        head[r] = (ids[k] != INT_MAX && (k == 0 || ids[k] != ids[k - 1])) ? 1u : 0u;
-        heads += head[r];
+        head[r] = run_head(keys, 4 * threadIdx.x + r);
+        heads += head[r] ? 1u : 0u;
     }
     uint32_t total;
-    uint32_t pos = block_exclusive_scan_256(heads, lds4, &total);
+    uint32_t u = block_exclusive_scan_256(heads, lds4, &total);
     const uint32_t base = offset[blockIdx.x];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+        const int k = 4 * threadIdx.x + r;
         if (head[r]) {
-            const int32_t id = ids[4 * threadIdx.x + r];
-            uniq[pos] = id;
-            nodes[base + pos] = id;
-            ++pos;
+            nodes[base + u] = static_cast<int32_t>(keys[k] >> 10);
+            node_start[base + u] = k;
+            ++u;
         }
+        if (keys[k] != kNoKey) pos_of_slot[keys[k] & 1023u] = static_cast<uint16_t>(k);
     }
     __syncthreads();
     const int64_t s = first + threadIdx.x;
     if (threadIdx.x < elems && s < ne) {
-        const int4 c = conn[s];
-        const int32_t v[4] = {c.x, c.y, c.z, c.w};
-        uint32_t packed = 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            int lo = 0, hi = static_cast<int>(total) - 1;
-            while (lo < hi) {  // first index with uniq[idx] >= v[a]
-                const int mid = (lo + hi) >> 1;
-                if (uniq[mid] < v[a]) lo = mid + 1;
-                else hi = mid;
-            }
-            packed |= static_cast<uint32_t>(lo & 0xff) << (8 * a);
-        }
-        lconn[s] = packed;
+        const int b = 4 * threadIdx.x;
+        elem_pos[s] = make_ushort4(pos_of_slot[b], pos_of_slot[b + 1], pos_of_slot[b + 2], pos_of_slot[b + 3]);
     }
+}
+
+// Number of patch references of every node (patch_nodes entries equal to it).
+__global__ __launch_bounds__(kThreads) void k_count_refs(const int32_t *nodes, int64_t refs, uint32_t *count) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (r < refs) atomicAdd(&count[nodes[r]], 1u);
 }
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
@@ -309,7 +318,11 @@ void free_mesh(nsasm_mesh *m) {
     device_free(m->x);
     device_free(m->patch_off);
     device_free(m->patch_nodes);
-    device_free(m->lconn);
+    device_free(m->patch_node_start);
+    device_free(m->elem_pos);
+    device_free(m->node_ref_off);
+    device_free(m->ref_slot);
+    device_free(m->partial);
     delete m;
 }
 
@@ -320,7 +333,8 @@ nsasm_status read_flags(const CreateFlags *d_flags, hipStream_t stream, CreateFl
 }
 
 // Build patches of `elems` consecutive mesh-order elements.  Returns
-// UNSUPPORTED (without touching m) when a patch has too many distinct nodes.
+// UNSUPPORTED (leaving m without patches) when a patch has too many distinct
+// nodes.
 nsasm_status build_patches(nsasm_mesh *m, int elems, hipStream_t stream) {
     const int64_t np = (m->n_elems + elems - 1) / elems;
     if (np >= INT_MAX) return fail(NSASM_ERR_UNSUPPORTED, "too many patches");
@@ -348,10 +362,16 @@ nsasm_status build_patches(nsasm_mesh *m, int elems, hipStream_t stream) {
         if (err != hipSuccess) st = hip_fail(err, "patch offsets");
     }
     if (st == NSASM_OK) st = device_alloc(&m->patch_nodes, total, "patch nodes");
-    if (st == NSASM_OK) st = device_alloc(&m->lconn, static_cast<size_t>(m->n_elems), "patch local ids");
+    // one padding entry so that reading the successor of the last reference stays in bounds
+    if (st == NSASM_OK) st = device_alloc(&m->patch_node_start, static_cast<size_t>(total) + 1, "patch slot starts");
+    if (st == NSASM_OK) {
+        hipError_t err = hipMemsetAsync(m->patch_node_start + total, 0, sizeof(int32_t), stream);
+        if (err != hipSuccess) st = hip_fail(err, "patch slot padding");
+    }
+    if (st == NSASM_OK) st = device_alloc(&m->elem_pos, static_cast<size_t>(m->n_elems), "element slots");
     if (st == NSASM_OK) {
         k_patch_fill<<<static_cast<unsigned>(np), kThreads, 0, stream>>>(
-            m->conn, m->n_elems, elems, count, m->patch_nodes, m->lconn);
+            m->conn, m->n_elems, elems, count, m->patch_nodes, m->patch_node_start, m->elem_pos);
         st = check_launch("k_patch_fill");
     }
     if (st == NSASM_OK) {
@@ -361,9 +381,11 @@ nsasm_status build_patches(nsasm_mesh *m, int elems, hipStream_t stream) {
     if (st != NSASM_OK) {
         device_free(count);
         device_free(m->patch_nodes);
-        device_free(m->lconn);
+        device_free(m->patch_node_start);
+        device_free(m->elem_pos);
         m->patch_nodes = nullptr;
-        m->lconn = nullptr;
+        m->patch_node_start = nullptr;
+        m->elem_pos = nullptr;
         return st;
     }
     m->patch_off = reinterpret_cast<int32_t *>(count);
@@ -371,6 +393,58 @@ nsasm_status build_patches(nsasm_mesh *m, int elems, hipStream_t stream) {
     m->patch_elems = elems;
     m->max_patch_nodes = static_cast<int32_t>(max_nodes);
     m->patch_node_refs = total;
+    return NSASM_OK;
+}
+
+// Node-major index of the patch references (for the deterministic gather of
+// per-patch partial sums) and the partial-sum buffer itself.
+nsasm_status build_node_gather(nsasm_mesh *m, hipStream_t stream) {
+    const int64_t nn = m->n_nodes, refs = m->patch_node_refs;
+    uint32_t *off = nullptr, *keys = nullptr;
+    NSASM_TRY(device_alloc(&off, static_cast<size_t>(nn + 1), "node reference offsets"));
+    nsasm_status st = device_alloc(&keys, static_cast<size_t>(refs), "node reference keys");
+    int32_t *refs_sorted = nullptr;
+    if (st == NSASM_OK) st = device_alloc(&refs_sorted, static_cast<size_t>(refs), "node references");
+    if (st == NSASM_OK) st = device_alloc(&m->ref_slot, static_cast<size_t>(refs), "reference slots");
+    if (st == NSASM_OK) st = device_alloc(&m->partial, static_cast<size_t>(3 * refs), "patch partial sums");
+    if (st == NSASM_OK) {
+        hipError_t err = hipMemsetAsync(off, 0, sizeof(uint32_t) * (nn + 1), stream);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(keys, m->patch_nodes, sizeof(uint32_t) * refs, hipMemcpyDeviceToDevice, stream);
+        if (err != hipSuccess) st = hip_fail(err, "node reference setup");
+    }
+    if (st == NSASM_OK) {
+        k_count_refs<<<blocks_for(refs), kThreads, 0, stream>>>(m->patch_nodes, refs, off);
+        st = check_launch("k_count_refs");
+    }
+    if (st == NSASM_OK) st = exclusive_scan_u32(off, off, nn + 1, nullptr, stream);
+    if (st == NSASM_OK) {
+        k_iota<<<blocks_for(refs), kThreads, 0, stream>>>(refs_sorted, refs);
+        st = check_launch("k_iota");
+    }
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < nn) ++bits;
+    // stable: each node's references stay in patch order
+    if (st == NSASM_OK) st = radix_sort_pairs_u32(keys, refs_sorted, refs, bits, stream);
+    if (st == NSASM_OK) {
+        k_invert<<<blocks_for(refs), kThreads, 0, stream>>>(refs_sorted, refs, m->ref_slot);
+        st = check_launch("k_invert");
+    }
+    if (st == NSASM_OK) {
+        hipError_t err = hipStreamSynchronize(stream);
+        if (err != hipSuccess) st = hip_fail(err, "node gather build");
+    }
+    device_free(keys);
+    device_free(refs_sorted);
+    if (st != NSASM_OK) {
+        device_free(off);
+        device_free(m->ref_slot);
+        device_free(m->partial);
+        m->ref_slot = nullptr;
+        m->partial = nullptr;
+        return st;
+    }
+    m->node_ref_off = reinterpret_cast<int32_t *>(off);
     return NSASM_OK;
 }
 
@@ -461,7 +535,8 @@ nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64
         const int elems = opt.patch_elems > 0 ? opt.patch_elems : kMaxPatchElems;
         nsasm_status st = build_patches(m, elems, stream);
         if (st == NSASM_OK) {
-            m->scatter = NSASM_SCATTER_PATCH;
+            m->scatter = (opt.scatter == NSASM_SCATTER_PATCH) ? NSASM_SCATTER_PATCH : NSASM_SCATTER_PATCH_GATHER;
+            if (m->scatter == NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(build_node_gather(m, stream));
         } else if (!(st == NSASM_ERR_UNSUPPORTED && opt.scatter == NSASM_SCATTER_AUTO)) {
             return st;
         }
@@ -515,7 +590,7 @@ extern "C" nsasm_status nsasm_mesh_create(const double *coords, int64_t n_nodes,
     if (opts) opt = *opts;
     if (opt.renumber != 0 && opt.renumber != 1)
         return fail(NSASM_ERR_INVALID_ARGUMENT, "renumber must be 0 or 1");
-    if (opt.scatter < NSASM_SCATTER_AUTO || opt.scatter > NSASM_SCATTER_PATCH)
+    if (opt.scatter < NSASM_SCATTER_AUTO || opt.scatter > NSASM_SCATTER_PATCH_GATHER)
         return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown scatter mode %d", opt.scatter);
     if (opt.patch_elems != 0 &&
         (opt.patch_elems < 32 || opt.patch_elems > kMaxPatchElems || opt.patch_elems % 32 != 0))

@@ -56,7 +56,7 @@ def test_patches_cover_elements():
     mesh = _mesh(m.coords, m.conn)
     info = mesh.info
     log(f"info {info}")
-    assert info["scatter"] == "patch" and info["renumbered"] == 1
+    assert info["scatter"] == "patch_gather" and info["renumbered"] == 1
     assert info["n_patches"] == -(-m.n_elems // 256)
     assert m.n_nodes <= info["patch_node_refs"] <= 4 * m.n_elems
     assert info["max_patch_nodes"] <= 256
@@ -101,7 +101,7 @@ def test_unused_nodes_and_single_element():
     prm = oracle.Params(1.3, 0.01, 0.1, synth.BODY_FORCE)
     ref = oracle.rhs(coords, conn, u, p, prm)
     refg = oracle.vjp(coords, conn, u, 2 * u, prm)
-    for scatter in ("atomic", "patch"):
+    for scatter in ("atomic", "patch", "patch_gather"):
         for renumber in (False, True):
             mesh = _mesh(coords, conn, scatter=scatter, renumber=renumber)
             ut = mesh.to_mesh_order(torch.from_numpy(u).to(dev))

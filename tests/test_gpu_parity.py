@@ -26,7 +26,8 @@ SMALL = [
     Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1),
 ]
 MODES = [dict(scatter="atomic", renumber=False), dict(scatter="atomic", renumber=True),
-         dict(scatter="patch", renumber=True), dict(scatter="auto", renumber=True, patch_elems=64)]
+         dict(scatter="patch", renumber=True), dict(scatter="patch_gather", renumber=True),
+         dict(scatter="auto", renumber=True, patch_elems=64)]
 
 
 def _ids(cases):
@@ -53,7 +54,7 @@ def test_vjp_fp64(case, mode):
     assert err <= TOL64
 
 
-@pytest.mark.parametrize("scatter", ["atomic", "patch"])
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
 @pytest.mark.parametrize("case", [SMALL[1], SMALL[4], SMALL[6]], ids=_ids([SMALL[1], SMALL[4], SMALL[6]]))
 def test_mixed_precision(case, scatter):
     log(f"mixed {case.label()} {scatter}")
@@ -68,9 +69,9 @@ def test_patch_sizes_and_info():
     case = Case(5, jitter=True, permute=True, mu=1e-4, cs=0.1)
     ref = None
     for pe in (32, 96, 160, 256):
-        pr = Prepared(case, scatter="patch", patch_elems=pe)
+        pr = Prepared(case, scatter="patch_gather", patch_elems=pe)
         info = pr.mesh.info
-        assert info["scatter"] == "patch" and info["patch_elems"] == pe
+        assert info["scatter"] == "patch_gather" and info["patch_elems"] == pe
         assert info["n_patches"] == -(-pr.m.n_elems // pe)
         assert 4 <= info["max_patch_nodes"] <= 256
         r = pr.rhs()
@@ -86,17 +87,18 @@ def test_auto_falls_back_to_atomic_without_renumbering():
     case = Case(12, jitter=True, permute=True)
     pr = Prepared(case, scatter="auto", renumber=False)
     # shuffle elements too, so user order has no locality at all
-    assert pr.mesh.info["scatter"] in ("atomic", "patch")
+    assert pr.mesh.info["scatter"] in ("atomic", "patch", "patch_gather")
     m = pr.m
     rng = np.random.default_rng(3)
     conn = m.conn[rng.permutation(m.n_elems)]
     dev = torch.device("cuda")
     mesh = api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(conn).to(dev), renumber=False)
     assert mesh.info["scatter"] == "atomic"
-    with pytest.raises(api.NsasmError) as ei:
-        api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(conn).to(dev), renumber=False,
-                 scatter="patch")
-    assert ei.value.status_name == "UNSUPPORTED"
+    for scatter in ("patch", "patch_gather"):
+        with pytest.raises(api.NsasmError) as ei:
+            api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(conn).to(dev), renumber=False,
+                     scatter=scatter)
+        assert ei.value.status_name == "UNSUPPORTED"
 
 
 def test_accumulate_flag():
@@ -115,12 +117,21 @@ def test_accumulate_flag():
     assert oracle.rel_l2(g2.cpu().numpy(), g1.cpu().numpy() + 1) < 1e-14
 
 
-def test_repeat_runs_agree():
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+def test_repeat_runs_agree(scatter):
+    """Atomic scatters agree to rounding; the gather scatter is bitwise
+    reproducible."""
     from paper_2403_08777_amd import api
 
-    pr = Prepared(Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1))
-    u, p, _ = pr.fields(torch.float64)
-    a = api.assemble_rhs(pr.mesh, u, p, pr.case.params()).cpu().numpy()
+    pr = Prepared(Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1), scatter=scatter)
+    u, p, lam = pr.fields(torch.float64)
+    prm = pr.case.params()
+    a = api.assemble_rhs(pr.mesh, u, p, prm).cpu().numpy()
+    ga = api.assemble_rhs_vjp(pr.mesh, u, lam, prm).cpu().numpy()
     for _ in range(3):
-        b = api.assemble_rhs(pr.mesh, u, p, pr.case.params()).cpu().numpy()
-        assert oracle.rel_l2(b, a) <= 1e-14
+        b = api.assemble_rhs(pr.mesh, u, p, prm).cpu().numpy()
+        gb = api.assemble_rhs_vjp(pr.mesh, u, lam, prm).cpu().numpy()
+        if scatter == "patch_gather":
+            assert np.array_equal(a, b) and np.array_equal(ga, gb)
+        else:
+            assert oracle.rel_l2(b, a) <= 1e-14 and oracle.rel_l2(gb, ga) <= 1e-14
