@@ -23,7 +23,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-FP64_PEAK_TFS = 78.6           # MI355X FP64 vector, vendor figure
+FP64_PEAK_TFS = 78.6           # MI355X FP64 vector: 256 CUs x 2.4 GHz x 128 flop/cycle
+
+# Floating-point operations per element of the assembly as the kernels compute
+# it (add/sub/mul = 1, FMA = 2, divide/sqrt/cbrt = 1): geometry 58, velocity
+# gradient 54, pressure gradient 18 (forward) or adjoint gradient 54 (VJP),
+# element terms, plus 12 additions of the scatter-add.  Smagorinsky adds the
+# strain norm, filter width and (VJP) its derivative.
+FLOPS_PER_ELEMENT = {("fwd", False): 281, ("fwd", True): 317, ("vjp", False): 463, ("vjp", True): 538}
+
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
 def algorithmic_bytes(ne: int, nn: int, mode: str, elem_bytes: int) -> float:
@@ -36,6 +45,40 @@ def algorithmic_bytes(ne: int, nn: int, mode: str, elem_bytes: int) -> float:
     if mode == "fwd":        # x, u, p in; rhs out
         return conn + x + vec + elem_bytes * nn + vec
     return conn + x + vec + vec + vec   # x, u, adjoint in; grad out
+
+
+def kernel_label(scatter: str, mode: str) -> str:
+    name = {"patch_gather": "k_assemble_patch + k_gather_partials", "patch": "k_assemble_patch",
+            "atomic": "k_assemble_atomic"}[scatter]
+    return f"{name} ({'forward' if mode == 'fwd' else 'VJP'}, FP64)"
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources, to tell whether stored counters are current."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_08777_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, mode: str, scatter: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary of this workload, or None if there is none or the kernels changed
+    since it was taken."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest() or rec.get("scatter") != scatter:
+        return None
+    entry = rec.get("calls", {}).get(mode)
+    return None if entry is None else entry.get("bytes")
 
 
 def parse():
@@ -125,8 +168,9 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_per_step:.4f} ms/step (wall {wall_ms / args.steps:.4f}), "
         f"{value / 1e9:.2f} G elem/s fwd+VJP")
 
-    # per-kernel durations: the assembly kernels alone (ACCUMULATE skips the
-    # zero-fill kernel), HIP events on the launch stream
+    # per-call durations of the assembly kernels alone, HIP events on the
+    # launch stream; with atomic scatter, ACCUMULATE skips the zero-fill
+    # kernel (the gather scatter has none)
     def kernel_ms(fn, reps):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
@@ -138,8 +182,9 @@ def main():
         return float(np.mean(t)), float(np.median(t)), t[0], t[-1]
 
     scratch = torch.zeros_like(u)
-    fwd_k = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, prm, out=scratch, accumulate=True), args.kernel_reps)
-    vjp_k = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, prm, out=scratch, accumulate=True),
+    acc = mesh.info["scatter"] != "patch_gather"
+    fwd_k = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, prm, out=scratch, accumulate=acc), args.kernel_reps)
+    vjp_k = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, prm, out=scratch, accumulate=acc),
                       args.kernel_reps)
     fill_k = kernel_ms(lambda: scratch.zero_(), args.kernel_reps)
     kernels = {
@@ -149,10 +194,15 @@ def main():
                 "alg_bytes": algorithmic_bytes(ne, nn, "vjp", 8)},
         "zero_fill_equiv": {"mean_ms": fill_k[0]},
     }
+    eddy = wl.cs > 0
     for k in ("fwd", "vjp"):
         kk = kernels[k]
         kk["elems_per_s"] = ne / (kk["mean_ms"] * 1e-3)
         kk["alg_GBs"] = kk["alg_bytes"] / (kk["mean_ms"] * 1e-3) / 1e9
+        kk["alg_flops"] = FLOPS_PER_ELEMENT[(k, eddy)] * ne
+        kk["alg_TFs"] = kk["alg_flops"] / (kk["mean_ms"] * 1e-3) / 1e12
+        kk["hbm_frac"] = kk["alg_GBs"] / HBM_PEAK_GBS
+        kk["fp64_frac"] = kk["alg_TFs"] / FP64_PEAK_TFS
     dom = max(("fwd", "vjp"), key=lambda k: kernels[k]["mean_ms"])
     kd = kernels[dom]
     log(f"[bench] kernels: fwd {fwd_k[0]:.4f} ms, vjp {vjp_k[0]:.4f} ms (dominant: {dom})")
@@ -197,9 +247,11 @@ def main():
                                f"relabelled={wl.permute}", "n_elems": ne, "n_nodes": nn, "mu": wl.mu,
                    "smagorinsky_cs": wl.cs, "scatter": mesh.info["scatter"],
                    "patch_elems": mesh.info["patch_elems"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_assemble_{mesh.info['scatter']} ({dom})",
-                     "achieved": kd["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["alg_GBs"] / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": kernel_label(mesh.info["scatter"], dom),
+                     "achieved": kd["alg_TFs"], "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": kd["alg_TFs"] / FP64_PEAK_TFS,
+                     "traffic": measured_traffic(wl.name, dom, mesh.info["scatter"]),
+                     "flops_per_element": FLOPS_PER_ELEMENT[(dom, eddy)], "elements_per_launch": ne},
         "kernels": kernels,
         "forms": forms,
         "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms},

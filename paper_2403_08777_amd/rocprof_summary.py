@@ -1,0 +1,135 @@
+"""Turn rocprofv3 output into the short text summaries kept under profiles/.
+
+    python -m paper_2403_08777_amd.rocprof_summary stats KERNEL_STATS_CSV --command CMD
+    python -m paper_2403_08777_amd.rocprof_summary traffic --fetch F --write W \\
+        --workload NAME --command-fetch CMD --command-write CMD
+
+``stats`` prints a markdown table of per-kernel call counts and durations from
+a ``--kernel-trace --stats -f csv`` run.  ``traffic`` reads two ``--pmc`` runs
+(FETCH_SIZE, then WRITE_SIZE; CSV or rocpd database), scales each counter by
+what it reads for the plain 1 GiB device copy that ``bench.py
+--copy-calibration`` performs, and prints a JSON record of the HBM bytes per
+assembly call (forward, VJP) tagged with a digest of the HIP sources, which
+``bench.py`` uses only while the kernels are unchanged.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_08777_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short_name(name: str) -> str:
+    name = name.replace("nsasm::(anonymous namespace)::", "")
+    m = re.match(r"(?:void )?([\w:]+(?:<[^()]*>)?)", name)
+    return m.group(1) if m else name[:60]
+
+
+def read_counters(path: str):
+    """[(kernel name, grid size, counter, value)] from a CSV or rocpd DB."""
+    rows = []
+    if path.endswith(".db"):
+        con = sqlite3.connect(path)
+        cur = con.execute("select kernel_name, grid_size, counter_name, value from counters_collection")
+        rows = [(k, int(g), c, float(v)) for k, g, c, v in cur]
+    else:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def median_by_kernel(rows, counter):
+    """Median per-dispatch value of `counter` for each (kernel, grid size)."""
+    acc = defaultdict(list)
+    for k, g, c, v in rows:
+        if c == counter:
+            acc[(short_name(k), g)].append(v)
+    return {key: sorted(v)[len(v) // 2] for key, v in acc.items()}
+
+
+def copy_scale(rows, counter):
+    """Bytes per counter unit, from the 1 GiB device copy (the largest copy
+    dispatch of the run)."""
+    kib = max((v for k, g, c, v in rows if c == counter and "copyBuffer" in k), default=None)
+    if not kib:
+        raise SystemExit("no copy kernel found: run bench.py with --copy-calibration")
+    return COPY_BYTES / (kib * 1024.0), kib
+
+
+def traffic(args):
+    f_rows, w_rows = read_counters(args.fetch), read_counters(args.write)
+    fetch, write = median_by_kernel(f_rows, "FETCH_SIZE"), median_by_kernel(w_rows, "WRITE_SIZE")
+    fs, fkib = copy_scale(f_rows, "FETCH_SIZE")
+    ws, wkib = copy_scale(w_rows, "WRITE_SIZE")
+    calls = {}
+    for mode, tag in (("fwd", "0"), ("vjp", "1")):
+        parts = [key for key in fetch if key[0].startswith("k_assemble_patch<double") and
+                 key[0].split(",")[2].strip() == tag]
+        gathers = [key for key in fetch if key[0] == "k_gather_partials<double>"]
+        keys = parts + gathers
+        if not parts:
+            continue
+        fb = sum(fetch[k] for k in keys) * 1024.0 * fs
+        wb = sum(write.get(k, 0.0) for k in keys) * 1024.0 * ws
+        calls[mode] = {"kernels": [f"{k[0]} (grid {k[1]})" for k in keys], "fetch_bytes": fb,
+                       "write_bytes": wb, "bytes": fb + wb}
+    rec = {"workload": args.workload, "scatter": args.scatter, "source_sha256": source_digest(),
+           "command_fetch": args.command_fetch, "command_write": args.command_write,
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": fkib, "write_kib": wkib,
+                                "fetch_scale": fs, "write_scale": ws},
+           "calls": calls}
+    json.dump(rec, sys.stdout, indent=1)
+    print()
+
+
+def stats(args):
+    with open(args.csv) as f:
+        rows = list(csv.DictReader(f))
+    print(f"Command: `{args.command}`\n")
+    print("| kernel | calls | avg us | min us | max us | total % |")
+    print("|---|---:|---:|---:|---:|---:|")
+    for r in rows[: args.top]:
+        print(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+              f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--scatter", default="patch_gather")
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    args = ap.parse_args()
+    (stats if args.cmd == "stats" else traffic)(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,86 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (renumbering on, default scatter), against the full FP64 oracle run on
+the host cores.  Mixed precision: error against the FP64 oracle, printed and
+loosely gated."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2403_08777_amd import synth
+from tests.gpu_helpers import log
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+_CACHE = {}
+
+
+def _case(name):
+    """(workload, mesh, u, p, lam, gpu Mesh, mesh-ordered fields per dtype)."""
+    if name in _CACHE:
+        return _CACHE[name]
+    from paper_2403_08777_amd import api
+
+    wl = synth.WORKLOADS[name]
+    m, u, p, lam = synth.build(wl)
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev))
+    log(f"{name}: {m.n_elems} tets, {m.n_nodes} nodes, info {mesh.info}")
+    _CACHE.clear()  # keep one large case resident at a time
+    _CACHE[name] = (wl, m, u, p, lam, mesh)
+    return _CACHE[name]
+
+
+def _params(wl):
+    from paper_2403_08777_amd import api
+
+    return api.Params(wl.rho, wl.mu, wl.cs, wl.body_force), oracle.Params(wl.rho, wl.mu, wl.cs, wl.body_force)
+
+
+def _run(mesh, fn, dtype, *fields):
+    dev = torch.device("cuda")
+    ts = [mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(f)).to(dev, dtype)) for f in fields]
+    out = fn(mesh, *ts)
+    return mesh.from_mesh_order(out).double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["cube96_perm", "cube160_jit_perm_smag", "cube96_jit_perm"])
+def test_forward_fp64_full(name):
+    from paper_2403_08777_amd import api
+
+    wl, m, u, p, lam, mesh = _case(name)
+    prm, oprm = _params(wl)
+    got = _run(mesh, lambda ms, a, b: api.assemble_rhs(ms, a, b, prm), torch.float64, u, p)
+    ref = oracle.rhs(m.coords, m.conn, u, p, oprm)
+    err = oracle.rel_l2(got, ref)
+    log(f"{name} fp64 forward rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["cube96_jit_perm", "cube160_jit_perm_smag"])
+def test_vjp_fp64_full(name):
+    from paper_2403_08777_amd import api
+
+    wl, m, u, p, lam, mesh = _case(name)
+    prm, oprm = _params(wl)
+    got = _run(mesh, lambda ms, a, b: api.assemble_rhs_vjp(ms, a, b, prm), torch.float64, u, lam)
+    ref = oracle.vjp(m.coords, m.conn, u, lam, oprm)
+    err = oracle.rel_l2(got, ref)
+    log(f"{name} fp64 vjp rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_mixed_full_160():
+    """Mixed precision on the 160^3 jittered mesh with Smagorinsky: FP64
+    geometry, FP32 fields/arithmetic/scatter; error against the FP64 oracle."""
+    from paper_2403_08777_amd import api
+
+    wl, m, u, p, lam, mesh = _case("cube160_jit_perm_smag")
+    prm, oprm = _params(wl)
+    r32 = _run(mesh, lambda ms, a, b: api.assemble_rhs(ms, a, b, prm), torch.float32, u, p)
+    g32 = _run(mesh, lambda ms, a, b: api.assemble_rhs_vjp(ms, a, b, prm), torch.float32, u, lam)
+    er = oracle.rel_l2(r32, oracle.rhs(m.coords, m.conn, u, p, oprm))
+    eg = oracle.rel_l2(g32, oracle.vjp(m.coords, m.conn, u, lam, oprm))
+    log(f"cube160 mixed rel_l2: rhs {er:.3e}, grad {eg:.3e}")
+    assert er <= 1e-4 and eg <= 1e-4
