@@ -4,10 +4,10 @@
  *
  * The operation is the RHS assembly of an explicit-momentum fractional-step LES
  * (Owen, Ernst et al., "Alya towards Exascale", Sec. II), specialised as in
- * Sec. IV-B: linear tetrahedra (4 nodes, constant shape-function gradients),
+ * Sec. V-B: linear tetrahedra (4 nodes, constant shape-function gradients),
  * constant density and viscosity, an eddy viscosity evaluated once per element
  * on the fly, and the elemental RHS computed directly without elemental
- * matrices (Sec. IV-A).  For element e with vertices a = 0..3 and nodal
+ * matrices (Sec. V-A).  For element e with vertices a = 0..3 and nodal
  * velocity u_a, pressure p_a:
  *
  *   J = [x1-x0 | x2-x0 | x3-x0],  V = |det J| / 6,
@@ -116,7 +116,7 @@ typedef struct {
  * Build a mesh: validate the connectivity, then (renumber = 1) order elements
  * along a Morton curve of their centroids, renumber nodes in order of first
  * use by that element order, and cut the element sequence into patches.
- * Locality of nodal gathers and scatters is what this buys (Sec. IV-C:
+ * Locality of nodal gathers and scatters is what this buys (Sec. V-C:
  * indirect nodal accesses dominate once intermediates live in registers, and
  * nodal reuse happens in the cache shared by the threads).
  *

@@ -5,7 +5,7 @@
  * incompressible Navier-Stokes momentum right-hand side over linear tetrahedra
  * (the RHS assembly of Sec. II, specialised to P1 tetrahedra with four Gauss
  * points, constant density and viscosity and an eddy viscosity computed once per
- * element as in Sec. IV-B).  Only the tests, the smoke check and the CPU-baseline
+ * element as in Sec. V-B).  Only the tests, the smoke check and the CPU-baseline
  * leg of the benchmark load it.  It shares no source with the GPU library.
  *
  * The paper does not print the discrete equations (it defers them to the Alya

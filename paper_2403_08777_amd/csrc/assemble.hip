@@ -6,7 +6,7 @@
 //   c_2 = d_3 x d_1, c_3 = d_1 x d_2, det J = d_1 . c_1, grad N_k = c_k / det J,
 //   grad N_0 = -(grad N_1 + grad N_2 + grad N_3), V = |det J| / 6.
 //
-//   The paper integrates with four Gauss points on P1 tetrahedra (Sec. IV-B).
+//   The paper integrates with four Gauss points on P1 tetrahedra (Sec. V-B).
 //   Because grad N, G = grad u and q = grad p are constant on the element, the
 //   Gauss sums collapse exactly: with N_a(g) = alpha (a == g) or beta, weight
 //   V/4, one has sum_g (V/4) N_a(g) = V/4 and sum_g (V/4) N_a(g) N_b(g) =
@@ -18,7 +18,7 @@
 //     R^e_a = b - G y_a,   b = (V/4)(rho f - q),
 //     y_a = (rho V / 20)(u_a + U) + mu_e V grad N_a.
 //   This is the paper's restructuring (compute each RHS entry directly, few
-//   live intermediates; Sec. IV-A) carried one step further: the four Gauss
+//   live intermediates; Sec. V-A) carried one step further: the four Gauss
 //   points are summed symbolically, not numerically.
 //
 //   VJP, g = (dR/du)^T lambda, per element with L = sum_a lambda_a,

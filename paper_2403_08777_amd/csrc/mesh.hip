@@ -3,7 +3,7 @@
 //
 // The paper's kernels gather nodal values and scatter RHS entries through the
 // connectivity, and after removing intermediates those indirect accesses are
-// what remains (Sec. IV-C); their reuse happens in the shared cache.  On a
+// what remains (Sec. V-C); their reuse happens in the shared cache.  On a
 // chip with eight L2 caches (one per XCD) that reuse depends on the order of
 // elements and on node numbering, so the mesh is reordered here once:
 //   1. elements sorted along a Morton curve of their centroids;
