@@ -13,7 +13,7 @@
  *   J = [x1-x0 | x2-x0 | x3-x0],  V = |det J| / 6,
  *   grad N_a = row a of J^-1 (a = 1..3),  grad N_0 = -(grad N_1 + grad N_2 + grad N_3),
  *   G = grad u = sum_a u_a (x) grad N_a,  q = grad p = sum_a p_a grad N_a,
- *   mu_e = mu + rho (cs V^(1/3))^2 |S|,  S = (G + G^T)/2,  |S| = sqrt(2 S:S),
+ *   mu_e = mu + mu_t(G, V)  (eddy viscosity, see nsasm_params.eddy_model),
  *   R^e_a = int_e N_a (-rho G u_h - q + rho f) dx - mu_e V G grad N_a,
  *   rhs_n = sum over (e, a) with node(e, a) = n of R^e_a,
  *
@@ -83,13 +83,28 @@ typedef enum {
 /* Set in nsasm_params.flags: add into the output instead of overwriting it. */
 #define NSASM_ACCUMULATE 1u
 
+/* Eddy-viscosity models (nsasm_params.eddy_model), both evaluated once per
+ * element from its constant velocity gradient G = grad u, with filter width
+ * Delta = V^(1/3) and C_s = smagorinsky_cs (Sec. V-B computes the model on the
+ * fly, once per element):
+ *   SMAGORINSKY: mu_t = rho (C_s Delta)^2 |S|, S = (G + G^T)/2, |S| = sqrt(2 S:S).
+ *   VREMAN (the paper's model; Vreman, Phys. Fluids 16, 2004): with
+ *     alpha_ij = du_j/dx_i, beta_ij = Delta^2 sum_m alpha_mi alpha_mj,
+ *     B = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2,
+ *     mu_t = rho c sqrt(B / alpha:alpha), c = 2.5 C_s^2, and mu_t = 0 where
+ *     alpha:alpha = 0 or B <= 0.
+ * The VJP differentiates mu_t, taking d mu_t / d G = 0 where the model is not
+ * differentiable (|S| = 0; B = 0). */
+#define NSASM_EDDY_SMAGORINSKY 0u
+#define NSASM_EDDY_VREMAN 1u
+
 typedef struct {
     double rho;            /* density, constant (> 0) */
     double mu;             /* molecular dynamic viscosity, constant (>= 0) */
-    double smagorinsky_cs; /* Smagorinsky constant; 0 disables the eddy viscosity */
+    double smagorinsky_cs; /* model constant C_s; 0 disables the eddy viscosity */
     double body_force[3];  /* constant body-force acceleration f; term is +rho f */
     uint32_t flags;        /* bitwise OR of NSASM_ACCUMULATE, or 0 */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t eddy_model;   /* NSASM_EDDY_SMAGORINSKY (0) or NSASM_EDDY_VREMAN */
 } nsasm_params;
 
 typedef struct {
@@ -166,7 +181,7 @@ nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_
  * Summation order across elements is unspecified (atomic adds), so results
  * may differ between calls by rounding.  Asynchronous on stream.
  * Errors: INVALID_ARGUMENT (null/host pointers, rho <= 0, mu < 0, cs < 0,
- * non-finite parameters, unknown precision or flags), DEVICE.
+ * non-finite parameters, unknown precision, flags or eddy model), DEVICE.
  */
 nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
                                 nsasm_precision precision, const void *u, const void *p, void *rhs,
@@ -176,8 +191,8 @@ nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *para
  * Velocity vector-Jacobian product of the assembled RHS:
  *   grad_u = (d rhs / d u)^T adjoint,
  * recomputing the element quantities (nothing is stored by the forward call).
- * The pressure and body-force terms do not depend on u.  With cs > 0 the
- * derivative of mu_t uses d|S|/dG = 2 S / |S|, taken as 0 where |S| = 0.
+ * The pressure and body-force terms do not depend on u.  The eddy viscosity
+ * is differentiated as stated at nsasm_params.
  * u, adjoint : device, n_nodes x 3, mesh order.
  * grad_u     : device, n_nodes x 3, mesh order; overwritten (or added to with
  *              NSASM_ACCUMULATE).  Must not overlap the inputs.

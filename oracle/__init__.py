@@ -50,10 +50,11 @@ def _load():
     d = ctypes.c_double
     lib.oracle_default_threads.restype = ctypes.c_int
     lib.oracle_geometry.argtypes = [i64, dp, i64, ip, dp, dp]
-    lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, dp]
-    lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, dp, ctypes.c_int]
-    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, d, d, d, dp, dp, dp]
-    lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, dp, ctypes.c_int]
+    ci = ctypes.c_int
+    lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, ci, dp]
+    lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
+    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, d, d, d, dp, ci, dp, dp]
+    lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
     for fn in ("oracle_geometry", "oracle_eddy", "oracle_rhs", "oracle_rhs_complex", "oracle_vjp"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
@@ -83,16 +84,21 @@ def _check(status):
         raise ValueError(f"oracle: {_ERRORS.get(status, status)}")
 
 
-class Params:
-    """Physical parameters: density, molecular viscosity, Smagorinsky constant
-    (0 = no eddy viscosity) and constant body-force acceleration."""
+EDDY_MODELS = {"smagorinsky": 0, "vreman": 1}
 
-    def __init__(self, rho=1.0, mu=1e-3, cs=0.0, f=(0.1, -0.2, 0.3)):
+
+class Params:
+    """Physical parameters: density, molecular viscosity, model constant cs
+    (0 = no eddy viscosity; Smagorinsky constant, Vreman uses c = 2.5 cs^2),
+    constant body-force acceleration and the eddy-viscosity model."""
+
+    def __init__(self, rho=1.0, mu=1e-3, cs=0.0, f=(0.1, -0.2, 0.3), model="smagorinsky"):
         self.rho, self.mu, self.cs = float(rho), float(mu), float(cs)
         self.f = np.asarray(f, dtype=np.float64).reshape(3).copy()
+        self.model = EDDY_MODELS[model]
 
     def args(self):
-        return (self.rho, self.mu, self.cs, _ptr(self.f))
+        return (self.rho, self.mu, self.cs, _ptr(self.f), self.model)
 
 
 def default_threads() -> int:

@@ -49,6 +49,7 @@
 typedef struct {
     double rho, mu, cs;
     double f[3];
+    int model; /* eddy viscosity: 0 Smagorinsky, 1 Vreman; none when cs == 0 */
 } oracle_params;
 
 /* Symmetric 4-point rule on the tetrahedron, exact for degree 2. */
@@ -92,18 +93,22 @@ static int element_geometry(const double xe[4][3], double gradN[4][3], double *v
 
 #define SCALAR double
 #define SQRT_S sqrt
+#define RE_S(x) (x)
 #define FN(name) name##_r
 #include "element_body.inc"
 #undef SCALAR
 #undef SQRT_S
+#undef RE_S
 #undef FN
 
 #define SCALAR double complex
 #define SQRT_S csqrt
+#define RE_S(x) creal(x)
 #define FN(name) name##_c
 #include "element_body.inc"
 #undef SCALAR
 #undef SQRT_S
+#undef RE_S
 #undef FN
 
 /* --------------------------------------------------------------- helpers */
@@ -119,11 +124,66 @@ static int gather_element(int64_t nn, const double *x, const int32_t *conn, int6
     return 1;
 }
 
-static void set_params(oracle_params *prm, double rho, double mu, double cs, const double *f) {
+static void set_params(oracle_params *prm, double rho, double mu, double cs, const double *f, int model) {
     prm->rho = rho;
     prm->mu = mu;
     prm->cs = cs;
     for (int i = 0; i < 3; ++i) prm->f[i] = f[i];
+    prm->model = model;
+}
+
+/* D = d mu_t / d G (D_ij = d mu_t / d G_ij) at velocity gradient G, for the
+ * selected model; 0 where the model is not differentiable (|S| = 0 for
+ * Smagorinsky, B <= 0 or alpha:alpha = 0 for Vreman). */
+static void eddy_derivative(const double G[3][3], double vol, const oracle_params *prm, double D[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) D[i][j] = 0.0;
+    if (prm->cs <= 0.0) return;
+    const double delta = cbrt(vol);
+    if (prm->model != 1) {
+        /* mu_t = rho (cs Delta)^2 |S|, d|S|/dG = 2 S / |S| */
+        double S[3][3], smag;
+        (void)smagorinsky_r(G, vol, prm, S, &smag);
+        if (smag == 0.0) return;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                D[i][j] = prm->rho * (prm->cs * delta) * (prm->cs * delta) * 2.0 * S[i][j] / smag;
+        return;
+    }
+    /* Vreman: nu = c sqrt(B/aa); chain rule through beta(alpha) and B(beta) */
+    const double c = 2.5 * prm->cs * prm->cs;
+    double alpha[3][3], beta[3][3], aa = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            alpha[i][j] = G[j][i];
+            aa += alpha[i][j] * alpha[i][j];
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double b = 0;
+            for (int m = 0; m < 3; ++m) b += delta * delta * alpha[m][i] * alpha[m][j];
+            beta[i][j] = b;
+        }
+    const double B = beta[0][0] * beta[1][1] - beta[0][1] * beta[0][1] + beta[0][0] * beta[2][2] -
+                     beta[0][2] * beta[0][2] + beta[1][1] * beta[2][2] - beta[1][2] * beta[1][2];
+    if (aa == 0.0 || B <= 0.0) return;
+    /* dB/dbeta for the six independent entries (upper triangle) */
+    double dB[3][3] = {{beta[1][1] + beta[2][2], -2.0 * beta[0][1], -2.0 * beta[0][2]},
+                       {0.0, beta[0][0] + beta[2][2], -2.0 * beta[1][2]},
+                       {0.0, 0.0, beta[0][0] + beta[1][1]}};
+    const double root = sqrt(B / aa);
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            /* d beta_ij / d alpha_kl = Delta^2 (delta_il alpha_kj + delta_jl alpha_ki), i <= j */
+            double dBda = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = i; j < 3; ++j) {
+                    const double dbeta = delta * delta * ((i == l ? alpha[k][j] : 0.0) + (j == l ? alpha[k][i] : 0.0));
+                    dBda += dB[i][j] * dbeta;
+                }
+            const double dnu = c / (2.0 * root) * (dBda / aa - B * 2.0 * alpha[k][l] / (aa * aa));
+            D[l][k] = prm->rho * dnu; /* alpha_kl = G_lk */
+        }
 }
 
 static int n_threads_or_default(int nthreads) {
@@ -156,9 +216,9 @@ int oracle_geometry(int64_t nn, const double *x, int64_t ne, const int32_t *conn
 
 /* Per-element eddy viscosity mu_t (ne values). */
 int oracle_eddy(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-                double rho, double mu, double cs, const double *f, double *mu_t) {
+                double rho, double mu, double cs, const double *f, int model, double *mu_t) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f);
+    set_params(&prm, rho, mu, cs, f, model);
     for (int64_t e = 0; e < ne; ++e) {
         int32_t ids[4];
         double xe[4][3], gN[4][3], V, D, ue[4][3], pe[4] = {0, 0, 0, 0}, G[3][3], S[3][3], q[3], sm;
@@ -176,10 +236,10 @@ int oracle_eddy(int64_t nn, const double *x, int64_t ne, const int32_t *conn, co
  * thread sums into a private copy of rhs, the copies are added at the end in
  * thread order (deterministic for a fixed thread count). */
 int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-               const double *p, double rho, double mu, double cs, const double *f, double *rhs,
+               const double *p, double rho, double mu, double cs, const double *f, int model, double *rhs,
                int nthreads) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f);
+    set_params(&prm, rho, mu, cs, f, model);
     const int nt = n_threads_or_default(nthreads);
     double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
     if (!part) return ORACLE_NOMEM;
@@ -228,9 +288,9 @@ int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, con
 /* Complex-step form: velocity u_re + i u_im, real x and p; serial. */
 int oracle_rhs_complex(int64_t nn, const double *x, int64_t ne, const int32_t *conn,
                        const double *u_re, const double *u_im, const double *p, double rho,
-                       double mu, double cs, const double *f, double *r_re, double *r_im) {
+                       double mu, double cs, const double *f, int model, double *r_re, double *r_im) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f);
+    set_params(&prm, rho, mu, cs, f, model);
     double complex *acc = (double complex *)calloc((size_t)nn * 3, sizeof(double complex));
     if (!acc) return ORACLE_NOMEM;
     for (int64_t e = 0; e < ne; ++e) {
@@ -302,28 +362,26 @@ static void element_vjp(const double gN[4][3], double V, const double ue[4][3],
             }
         }
     }
-    const double dmu_scale =
-        (prm->cs > 0.0 && smag != 0.0)
-            ? prm->rho * (prm->cs * cbrt(V)) * (prm->cs * cbrt(V)) * 2.0 / smag
-            : 0.0;
+    double D[3][3]; /* d mu_t / d G */
+    eddy_derivative(G, V, prm, D);
     for (int b = 0; b < 4; ++b)
         for (int k = 0; k < 3; ++k) {
-            double lv = 0, sv = 0;
+            double lv = 0, dv = 0;
             for (int j = 0; j < 3; ++j) {
                 lv += gN[b][j] * Lam[k][j];
-                sv += S[k][j] * gN[b][j];
+                dv += D[k][j] * gN[b][j];
             }
-            ge[b][k] += -mu_e * V * lv - V * Phi * dmu_scale * sv;
+            ge[b][k] += -mu_e * V * lv - V * Phi * dv;
         }
 }
 
 /* Velocity vector-Jacobian product g = (dR/du)^T lam (nn x 3), FP64, OpenMP as
  * in oracle_rhs. */
 int oracle_vjp(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-               const double *lam, double rho, double mu, double cs, const double *f, double *grad,
+               const double *lam, double rho, double mu, double cs, const double *f, int model, double *grad,
                int nthreads) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f);
+    set_params(&prm, rho, mu, cs, f, model);
     const int nt = n_threads_or_default(nthreads);
     double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
     if (!part) return ORACLE_NOMEM;

@@ -35,7 +35,7 @@ class NsasmError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_double), ("mu", ctypes.c_double), ("smagorinsky_cs", ctypes.c_double),
-                ("body_force", ctypes.c_double * 3), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("body_force", ctypes.c_double * 3), ("flags", ctypes.c_uint32), ("eddy_model", ctypes.c_uint32)]
 
 
 class _MeshOptions(ctypes.Structure):
@@ -102,20 +102,25 @@ def _dev(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
     return t
 
 
+EDDY_MODELS = {"smagorinsky": 0, "vreman": 1}
+
+
 @dataclass
 class Params:
-    """Density, molecular viscosity, Smagorinsky constant (0 = off) and the
-    constant body-force acceleration."""
+    """Density, molecular viscosity, eddy-viscosity model constant C_s
+    (0 = no eddy viscosity), constant body-force acceleration and the model
+    ("smagorinsky", or "vreman" with c = 2.5 C_s^2)."""
 
     rho: float = 1.0
     mu: float = 1e-3
     cs: float = 0.0
     body_force: tuple = (0.1, -0.2, 0.3)
+    eddy_model: str = "smagorinsky"
 
     def c_struct(self, accumulate: bool = False) -> _Params:
         f = tuple(float(v) for v in self.body_force)
         return _Params(float(self.rho), float(self.mu), float(self.cs), (ctypes.c_double * 3)(*f),
-                       ACCUMULATE if accumulate else 0, 0)
+                       ACCUMULATE if accumulate else 0, EDDY_MODELS[self.eddy_model])
 
 
 class Mesh:

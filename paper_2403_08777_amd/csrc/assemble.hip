@@ -53,7 +53,7 @@ template <typename T>
 struct KParams {
     T rho;
     T mu;
-    T rho_cs2;     // rho * cs^2
+    T rho_c;       // rho * model constant: cs^2 (Smagorinsky) or 2.5 cs^2 (Vreman)
     T rho_f[3];    // rho * f
 };
 
@@ -114,21 +114,68 @@ __device__ inline void vector_gradient(const T (&gN)[4][3], const T (&ve)[4][3],
     }
 }
 
-// Smagorinsky: |S| with S = (G + G^T)/2, |S| = sqrt(2 S:S); returns S too.
-template <typename T>
-__device__ inline T strain_norm(const T (&G)[3][3], T (&S)[3][3]) {
-    T ss = T(0);
+enum EddyModel { kNoEddy = 0, kSmagorinsky = 1, kVreman = 2 };
+
+// Eddy viscosity mu_t of the element's constant velocity gradient G, with
+// filter width Delta = V^(1/3) and c = rho_c Delta^2; with WANT_D also
+// D = d mu_t / d G (0 where the model is not differentiable).
+//   Smagorinsky: mu_t = c |S|, S = (G + G^T)/2, |S| = sqrt(2 S:S),
+//                D = (2c / |S|) S.
+//   Vreman (alpha = G^T, beta = Delta^2 alpha^T alpha): with P = G G^T,
+//                A = tr P = alpha:alpha and B = e2(P) (sum of the principal
+//                2x2 minors, Vreman's B_beta / Delta^4), mu_t = c s with
+//                s = sqrt(B / A); since dA/dG = 2G and dB/dG = 2(tr(P) I - P)G,
+//                D = c / (A s) ((A - s^2) G - P G).
+template <typename T, int EDDY, bool WANT_D>
+__device__ inline T eddy_viscosity(const T (&G)[3][3], T vol, T rho_c, T (&D)[3][3]) {
+    if (EDDY == kNoEddy) return T(0);
+    const T delta = cube_root(vol);
+    const T c = rho_c * delta * delta;
+    if (EDDY == kSmagorinsky) {
+        T S[3][3], ss = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                S[i][j] = T(0.5) * (G[i][j] + G[j][i]);
+                ss += S[i][j] * S[i][j];
+            }
+        const T smag = sqrt(T(2) * ss);
+        if (WANT_D) {
+            const T k = (smag > T(0)) ? T(2) * c / smag : T(0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) D[i][j] = k * S[i][j];
+        }
+        return c * smag;
+    }
+    T Pm[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            S[i][j] = T(0.5) * (G[i][j] + G[j][i]);
-            ss += S[i][j] * S[i][j];
+        for (int j = i; j < 3; ++j) {
+            Pm[i][j] = G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2];
+            Pm[j][i] = Pm[i][j];
         }
-    return sqrt(T(2) * ss);
+    const T A = Pm[0][0] + Pm[1][1] + Pm[2][2];
+    const T B = Pm[0][0] * Pm[1][1] - Pm[0][1] * Pm[0][1] + Pm[0][0] * Pm[2][2] - Pm[0][2] * Pm[0][2] +
+                Pm[1][1] * Pm[2][2] - Pm[1][2] * Pm[1][2];
+    const bool live = (A > T(0)) && (B > T(0));
+    const T s = live ? sqrt(B / A) : T(0);
+    if (WANT_D) {
+        const T k = live ? c / (A * s) : T(0);
+        const T diag = A - s * s;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                D[i][j] = k * (diag * G[i][j] - (Pm[i][0] * G[0][j] + Pm[i][1] * G[1][j] + Pm[i][2] * G[2][j]));
+    }
+    return c * s;
 }
 
-template <typename T, bool EDDY>
+template <typename T, int EDDY>
 __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&pe)[4],
                                    const KParams<T> &P, T (&re)[4][3]) {
     T G[3][3];
@@ -139,13 +186,8 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
 #pragma unroll
         for (int j = 0; j < 3; ++j) q[j] = d1 * gN[1][j] + d2 * gN[2][j] + d3 * gN[3][j];
     }
-    T mu_e = P.mu;
-    if (EDDY) {
-        T S[3][3];
-        const T smag = strain_norm(G, S);
-        const T delta = cube_root(vol);
-        mu_e += P.rho_cs2 * delta * delta * smag;
-    }
+    T unused[3][3];
+    const T mu_e = P.mu + eddy_viscosity<T, EDDY, false>(G, vol, P.rho_c, unused);
     const T sc = P.rho * vol * T(0.05);
     const T sv = mu_e * vol;
     const T w4 = vol * T(0.25);
@@ -165,13 +207,12 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
     }
 }
 
-template <typename T, bool EDDY>
+template <typename T, int EDDY>
 __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
                                    const KParams<T> &P, T (&ge)[4][3]) {
     T G[3][3], Lam[3][3];
     vector_gradient(gN, ue, G);
     vector_gradient(gN, le, Lam);
-    T mu_e = P.mu;
     const T sc = P.rho * vol * T(0.05);
     T U[3], L[3];
 #pragma unroll
@@ -179,40 +220,27 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
         U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
         L[i] = le[0][i] + le[1][i] + le[2][i] + le[3][i];
     }
-    T M[3][3];
-    if (EDDY) {
-        T S[3][3];
-        const T smag = strain_norm(G, S);
-        const T delta = cube_root(vol);
-        const T c = P.rho_cs2 * delta * delta;
-        mu_e += c * smag;
+    T D[3][3];
+    const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
+    const T sv = mu_e * vol;
+    T se = T(0);  // V * (Lambda : G): weight of d mu_t / d G
+    if (EDDY != kNoEddy) {
         T phi = T(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) phi += Lam[i][j] * G[i][j];
-        const T kappa = (smag > T(0)) ? T(2) * c / smag : T(0);
-        const T se = vol * phi * kappa;
-        const T sv = mu_e * vol;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] +
-                              le[3][k] * ue[3][j];
-                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j] + se * S[k][j];
-            }
-    } else {
-        const T sv = mu_e * vol;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] +
-                              le[3][k] * ue[3][j];
-                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
-            }
+        se = vol * phi;
     }
+    T M[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
+            M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
+            if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
+        }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const T w0 = le[b][0] + L[0], w1 = le[b][1] + L[1], w2 = le[b][2] + L[2];
@@ -242,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_zero(T *p, int64_t n) {
 }
 
 // One thread per element; f0 = u, f1 = p (forward) or lambda (VJP).
-template <typename T, bool EDDY, int MODE>
+template <typename T, int EDDY, int MODE>
 __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const int4 *__restrict__ conn,
                                                                const double *__restrict__ x,
                                                                const T *__restrict__ f0,
@@ -293,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
 // sums in a fixed order.  GATHER = false adds each node sum to `out` with a
 // global atomic; GATHER = true stores it to the node-major partial-sum buffer
 // (position ref_slot of the patch reference), for k_gather_partials.
-template <typename T, bool EDDY, int MODE, bool GATHER>
+template <typename T, int EDDY, int MODE, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, const int32_t *__restrict__ patch_off,
     const int32_t *__restrict__ patch_nodes, const int32_t *__restrict__ patch_node_start,
@@ -427,7 +455,8 @@ nsasm_status check_params(const nsasm_params *p) {
     if (p->mu < 0.0) return fail(NSASM_ERR_INVALID_ARGUMENT, "mu must be >= 0");
     if (p->smagorinsky_cs < 0.0) return fail(NSASM_ERR_INVALID_ARGUMENT, "smagorinsky_cs must be >= 0");
     if (p->flags & ~NSASM_ACCUMULATE) return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
-    if (p->reserved != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "reserved must be 0");
+    if (p->eddy_model != NSASM_EDDY_SMAGORINSKY && p->eddy_model != NSASM_EDDY_VREMAN)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown eddy_model %u", p->eddy_model);
     return NSASM_OK;
 }
 
@@ -436,12 +465,13 @@ KParams<T> kernel_params(const nsasm_params &p) {
     KParams<T> k;
     k.rho = static_cast<T>(p.rho);
     k.mu = static_cast<T>(p.mu);
-    k.rho_cs2 = static_cast<T>(p.rho * p.smagorinsky_cs * p.smagorinsky_cs);
+    const double c = (p.eddy_model == NSASM_EDDY_VREMAN ? 2.5 : 1.0) * p.smagorinsky_cs * p.smagorinsky_cs;
+    k.rho_c = static_cast<T>(p.rho * c);
     for (int i = 0; i < 3; ++i) k.rho_f[i] = static_cast<T>(p.rho * p.body_force[i]);
     return k;
 }
 
-template <typename T, bool EDDY, int MODE>
+template <typename T, int EDDY, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, const T *f0, const T *f1, T *out,
                     bool accumulate, hipStream_t s) {
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
@@ -482,8 +512,10 @@ nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, con
     }
     const KParams<T> kp = kernel_params<T>(p);
     const T *a = static_cast<const T *>(f0), *b = static_cast<const T *>(f1);
-    if (p.smagorinsky_cs > 0.0) return launch<T, true, MODE>(m, kp, a, b, o, accumulate, s);
-    return launch<T, false, MODE>(m, kp, a, b, o, accumulate, s);
+    if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
+        return launch<T, kVreman, MODE>(m, kp, a, b, o, accumulate, s);
+    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, MODE>(m, kp, a, b, o, accumulate, s);
+    return launch<T, kNoEddy, MODE>(m, kp, a, b, o, accumulate, s);
 }
 
 nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, const void *f0,

@@ -26,17 +26,19 @@ class Case:
     mu: float = 1e-3
     cs: float = 0.0
     rho: float = 1.0
+    model: str = "smagorinsky"
 
     def params(self):
         from paper_2403_08777_amd import api
 
-        return api.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE)
+        return api.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, self.model)
 
     def oracle_params(self):
-        return oracle.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE)
+        return oracle.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, model=self.model)
 
     def label(self):
-        return f"n={self.n} jit={self.jitter} perm={self.permute} mu={self.mu} cs={self.cs}"
+        m = "" if self.model == "smagorinsky" else f" {self.model}"
+        return f"n={self.n} jit={self.jitter} perm={self.permute} mu={self.mu} cs={self.cs}{m}"
 
 
 class Prepared:

@@ -45,7 +45,7 @@ def test_struct_layout_matches_header(tmp_path):
 #include "nsasm.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(nsasm_params), offsetof(nsasm_params, body_force),
-         offsetof(nsasm_params, flags), offsetof(nsasm_params, reserved));
+         offsetof(nsasm_params, flags), offsetof(nsasm_params, eddy_model));
   printf("%zu %zu %zu\n", sizeof(nsasm_mesh_options), offsetof(nsasm_mesh_options, scatter),
          offsetof(nsasm_mesh_options, patch_elems));
   printf("%zu %zu %zu\n", sizeof(nsasm_mesh_info_t), offsetof(nsasm_mesh_info_t, scatter),
@@ -58,7 +58,7 @@ int main(void) {
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     p = [int(v) for v in lines[0].split()]
     assert p == [ctypes.sizeof(api._Params), api._Params.body_force.offset, api._Params.flags.offset,
-                 api._Params.reserved.offset]
+                 api._Params.eddy_model.offset]
     o = [int(v) for v in lines[1].split()]
     assert o == [ctypes.sizeof(api._MeshOptions), api._MeshOptions.scatter.offset,
                  api._MeshOptions.patch_elems.offset]
@@ -85,7 +85,7 @@ def test_host_side_argument_checks():
     assert lib.nsasm_mesh_create(dummy, 8, dummy, 1 << 29, None, None, ctypes.byref(h)) == 1
     assert lib.nsasm_mesh_create(dummy, 1 << 31, dummy, 1, None, None, ctypes.byref(h)) == 1
     # options
-    for opts in (api._MeshOptions(2, 0, 0, 0), api._MeshOptions(1, 3, 0, 0), api._MeshOptions(1, 0, 48, 0),
+    for opts in (api._MeshOptions(2, 0, 0, 0), api._MeshOptions(1, 4, 0, 0), api._MeshOptions(1, 0, 48, 0),
                  api._MeshOptions(1, 0, 512, 0), api._MeshOptions(1, 0, 0, 7)):
         assert lib.nsasm_mesh_create(dummy, 8, dummy, 1, ctypes.byref(opts), None, ctypes.byref(h)) == 1
     # NULL mesh everywhere

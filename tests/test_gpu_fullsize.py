@@ -84,3 +84,19 @@ def test_mixed_full_160():
     eg = oracle.rel_l2(g32, oracle.vjp(m.coords, m.conn, u, lam, oprm))
     log(f"cube160 mixed rel_l2: rhs {er:.3e}, grad {eg:.3e}")
     assert er <= 1e-4 and eg <= 1e-4
+
+
+def test_vreman_full_160():
+    """The paper's eddy-viscosity model on the 160^3 jittered mesh, FP64
+    forward and VJP against the oracle."""
+    from paper_2403_08777_amd import api
+
+    wl, m, u, p, lam, mesh = _case("cube160_jit_perm_smag")
+    prm = api.Params(wl.rho, wl.mu, wl.cs, wl.body_force, "vreman")
+    oprm = oracle.Params(wl.rho, wl.mu, wl.cs, wl.body_force, model="vreman")
+    r = _run(mesh, lambda ms, a, b: api.assemble_rhs(ms, a, b, prm), torch.float64, u, p)
+    g = _run(mesh, lambda ms, a, b: api.assemble_rhs_vjp(ms, a, b, prm), torch.float64, u, lam)
+    er = oracle.rel_l2(r, oracle.rhs(m.coords, m.conn, u, p, oprm))
+    eg = oracle.rel_l2(g, oracle.vjp(m.coords, m.conn, u, lam, oprm))
+    log(f"cube160 vreman fp64 rel_l2: rhs {er:.3e}, grad {eg:.3e}")
+    assert er <= 1e-12 and eg <= 1e-12

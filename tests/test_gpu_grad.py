@@ -12,11 +12,12 @@ from tests.gpu_helpers import Case, Prepared, log
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cs,mu", [(0.0, 1e-3), (0.1, 1e-4)])
-def test_vjp_central_fd_16(cs, mu):
+@pytest.mark.parametrize("cs,mu,model", [(0.0, 1e-3, "smagorinsky"), (0.1, 1e-4, "smagorinsky"),
+                                         (0.1, 1e-4, "vreman")])
+def test_vjp_central_fd_16(cs, mu, model):
     from paper_2403_08777_amd import api
 
-    case = Case(16, jitter=True, permute=True, mu=mu, cs=cs)
+    case = Case(16, jitter=True, permute=True, mu=mu, cs=cs, model=model)
     log(f"fd {case.label()}")
     pr = Prepared(case)
     u, p, lam = pr.fields(torch.float64)
@@ -32,9 +33,9 @@ def test_vjp_central_fd_16(cs, mu):
     assert abs(fd - gd) <= 1e-6 * abs(gd)
 
 
-@pytest.mark.parametrize("cs", [0.0, 0.1])
-def test_vjp_dense_jacobian_2(cs):
-    case = Case(2, jitter=True, permute=True, mu=1e-3, cs=cs)
+@pytest.mark.parametrize("cs,model", [(0.0, "smagorinsky"), (0.1, "smagorinsky"), (0.1, "vreman")])
+def test_vjp_dense_jacobian_2(cs, model):
+    case = Case(2, jitter=True, permute=True, mu=1e-3, cs=cs, model=model)
     pr = Prepared(case)
     jac = oracle.dense_jacobian_complex_step(pr.m.coords, pr.m.conn, pr.u, pr.p, case.oracle_params())
     ref = (jac.T @ pr.lam.reshape(-1)).reshape(-1, 3)

@@ -169,6 +169,11 @@ def test_bad_arguments_on_device():
     st = lib.nsasm_assemble_rhs(pr.mesh.handle, ctypes.byref(prm_bad), 0, u.data_ptr(), p.data_ptr(),
                                 out.data_ptr(), None)
     assert st == 1
+    prm_bad = pr.case.params().c_struct()
+    prm_bad.eddy_model = 7
+    st = lib.nsasm_assemble_rhs_vjp(pr.mesh.handle, ctypes.byref(prm_bad), 0, u.data_ptr(), lam.data_ptr(),
+                                    out.data_ptr(), None)
+    assert st == 1 and b"eddy_model" in lib.nsasm_last_error()
     # the mesh still works after the failures
     assert oracle.rel_l2(pr.rhs(), pr.oracle_rhs()) <= 1e-12
 

@@ -135,3 +135,39 @@ def test_repeat_runs_agree(scatter):
             assert np.array_equal(a, b) and np.array_equal(ga, gb)
         else:
             assert oracle.rel_l2(b, a) <= 1e-14 and oracle.rel_l2(gb, ga) <= 1e-14
+
+
+VREMAN = [Case(2, jitter=True, permute=True, mu=1e-4, cs=0.1, model="vreman"),
+          Case(7, jitter=True, permute=True, mu=1e-4, cs=0.1, model="vreman"),
+          Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1, model="vreman")]
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+@pytest.mark.parametrize("case", VREMAN, ids=_ids(VREMAN))
+def test_vreman_fp64(case, scatter):
+    log(f"vreman {case.label()} {scatter}")
+    pr = Prepared(case, scatter=scatter)
+    ef = oracle.rel_l2(pr.rhs(), pr.oracle_rhs())
+    eg = oracle.rel_l2(pr.vjp(), pr.oracle_vjp())
+    log(f"  rel_l2 rhs={ef:.3e} grad={eg:.3e}")
+    assert ef <= TOL64 and eg <= TOL64
+
+
+@pytest.mark.parametrize("case", VREMAN[1:], ids=_ids(VREMAN[1:]))
+def test_vreman_mixed(case):
+    pr = Prepared(case)
+    ef = oracle.rel_l2(pr.rhs(torch.float32), pr.oracle_rhs())
+    eg = oracle.rel_l2(pr.vjp(torch.float32), pr.oracle_vjp())
+    log(f"vreman mixed {case.label()}: rhs={ef:.3e} grad={eg:.3e}")
+    assert ef <= TOL_MIXED and eg <= TOL_MIXED
+
+
+def test_vreman_differs_from_smagorinsky():
+    from paper_2403_08777_amd import api
+
+    case = Case(6, jitter=True, permute=True, mu=1e-4, cs=0.1)
+    pr = Prepared(case)
+    u, p, _ = pr.fields(torch.float64)
+    rs = api.assemble_rhs(pr.mesh, u, p, case.params()).cpu().numpy()
+    rv = api.assemble_rhs(pr.mesh, u, p, api.Params(1.0, 1e-4, 0.1, case.params().body_force, "vreman")).cpu().numpy()
+    assert oracle.rel_l2(rv, rs) > 1e-8

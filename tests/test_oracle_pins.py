@@ -346,3 +346,95 @@ def test_thread_count_independence(oracle_lib):
     r1 = oracle.rhs(m.coords, m.conn, u, p, prm, nthreads=1)
     r4 = oracle.rhs(m.coords, m.conn, u, p, prm, nthreads=4)
     assert oracle.rel_l2(r4, r1) < 1e-15
+
+
+# ------------------------------------------------------- Vreman eddy viscosity
+
+def _vreman_closed(A, vol, rho, cs):
+    """Vreman's mu_t for a constant velocity gradient A (A_ij = du_i/dx_j),
+    through the invariants of P = A A^T: B = e2(P) = ((tr P)^2 - tr(P^2))/2
+    times Delta^4, alpha:alpha = tr P."""
+    P = A @ A.T
+    e2 = 0.5 * (np.trace(P) ** 2 - np.trace(P @ P))
+    delta2 = np.cbrt(vol) ** 2
+    return rho * 2.5 * cs * cs * delta2 * np.sqrt(max(e2, 0.0) / np.trace(P))
+
+
+def test_vreman_closed_forms(oracle_lib):
+    m = synth.cube_mesh(3, jitter=True)
+    vol, _ = oracle.geometry(m.coords, m.conn)
+    rho, cs = 1.3, 0.1
+    prm = oracle.Params(rho, 0.0, cs, model="vreman")
+    # pure shear: Vreman's model vanishes
+    shear = np.zeros((m.n_nodes, 3))
+    shear[:, 0] = 2.5 * m.coords[:, 1]
+    assert np.abs(oracle.eddy(m.coords, m.conn, shear, prm)).max() < 1e-15
+    # diagonal strain diag(a, b, c)
+    a, b, c = 0.8, -0.3, 0.5
+    strain = m.coords * np.array([a, b, c])
+    expect = rho * 2.5 * cs * cs * np.cbrt(vol) ** 2 * np.sqrt(
+        (a * a * b * b + a * a * c * c + b * b * c * c) / (a * a + b * b + c * c))
+    np.testing.assert_allclose(oracle.eddy(m.coords, m.conn, strain, prm), expect, rtol=1e-12)
+    # rigid rotation about z: mu_t = rho c Delta^2 |w| / sqrt(2)
+    w = 1.7
+    rot = np.stack([-w * m.coords[:, 1], w * m.coords[:, 0], 0 * m.coords[:, 2]], axis=1)
+    np.testing.assert_allclose(oracle.eddy(m.coords, m.conn, rot, prm),
+                               rho * 2.5 * cs * cs * np.cbrt(vol) ** 2 * w / np.sqrt(2), rtol=1e-12)
+    # general linear field against the invariant form
+    A = np.random.default_rng(41).standard_normal((3, 3))
+    np.testing.assert_allclose(oracle.eddy(m.coords, m.conn, m.coords @ A.T, prm),
+                               [_vreman_closed(A, v, rho, cs) for v in vol], rtol=1e-11)
+
+
+def test_exact_rational_vreman_linear_field(oracle_lib):
+    """Vreman on: exact checker with the closed-form per-element viscosity."""
+    coords, conn, xf = dyadic_mesh(2, 23)
+    A = np.array([[0.5, 1.0, -0.25], [0.0, -0.75, 0.5], [0.25, 0.0, 0.25]])
+    uf = xf @ A.T + np.array([0.125, -0.5, 0.25])
+    cs, rho, mu = 0.1, 1.0, 1e-4
+    vol_np = np.array([abs(np.linalg.det((xf[t[1:]] - xf[t[0]]).T)) / 6.0 for t in conn])
+    mu_elem = [Fraction(float(mu + _vreman_closed(A, v, rho, cs))) for v in vol_np]
+    uq = [[Fraction(float(v)) for v in row] for row in uf]
+    pz = [Fraction(0)] * len(coords)
+    fq = [Fraction(float(v)) for v in F]
+    ref = frac_to_np(exact.assemble_rhs(coords, conn, uq, pz, Fraction(1), Fraction(0), fq, mu_elem))
+    got = oracle.rhs(xf, conn, uf, np.zeros(len(coords)), oracle.Params(rho, mu, cs, F, model="vreman"))
+    assert oracle.rel_l2(got, ref) < 1e-13
+
+
+def test_vreman_invariance_and_vjp(oracle_lib):
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-4, 0.1, F, model="vreman")
+    r = oracle.rhs(m.coords, m.conn, u, p, prm)
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    t = rng.standard_normal(3)
+    r2 = oracle.rhs(m.coords @ Q.T + t, m.conn, u @ Q.T, p, oracle.Params(1.0, 1e-4, 0.1, Q @ F, model="vreman"))
+    assert oracle.rel_l2(r2, r @ Q.T) < 1e-13
+    # the model changes the result (it is wired in) but stays close to Smagorinsky's scale
+    rs = oracle.rhs(m.coords, m.conn, u, p, oracle.Params(1.0, 1e-4, 0.1, F))
+    assert 1e-8 < oracle.rel_l2(r, rs) < 1e-1
+
+
+def test_vreman_vjp_complex_step(oracle_lib):
+    m = synth.cube_mesh(2, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F, model="vreman")
+    jac = oracle.dense_jacobian_complex_step(m.coords, m.conn, u, p, prm)
+    g_ref = (jac.T @ lam.reshape(-1)).reshape(-1, 3)
+    assert oracle.rel_l2(oracle.vjp(m.coords, m.conn, u, lam, prm), g_ref) < 1e-12
+
+
+def test_vreman_vjp_central_fd_16(oracle_lib):
+    m = synth.cube_mesh(16, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    prm = oracle.Params(1.0, 1e-4, 0.1, F, model="vreman")
+    d = np.random.default_rng(5).standard_normal(u.shape)
+    h = 1e-6
+    fd = (np.sum(lam * oracle.rhs(m.coords, m.conn, u + h * d, p, prm)) -
+          np.sum(lam * oracle.rhs(m.coords, m.conn, u - h * d, p, prm))) / (2 * h)
+    gd = np.sum(oracle.vjp(m.coords, m.conn, u, lam, prm) * d)
+    assert abs(fd - gd) <= 1e-6 * abs(gd)
