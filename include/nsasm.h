@@ -202,6 +202,36 @@ nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *
                                     nsasm_precision precision, const void *u, const void *adjoint,
                                     void *grad_u, void *stream);
 
+/*
+ * Pressure vector-Jacobian product of the assembled RHS:
+ *   grad_p = (d rhs / d p)^T adjoint.
+ * The RHS depends on p only through the pressure-gradient term, which is
+ * linear in p (per element -(V/4) grad p at every vertex), so grad_p does not
+ * depend on u and the eddy viscosity plays no part.
+ * adjoint : device, n_nodes x 3, mesh order.
+ * grad_p  : device, n_nodes, mesh order; overwritten (or added to with
+ *           NSASM_ACCUMULATE).  Must not overlap adjoint.
+ * Errors and ordering as nsasm_assemble_rhs.
+ */
+nsasm_status nsasm_assemble_rhs_vjp_p(const nsasm_mesh *mesh, const nsasm_params *params,
+                                      nsasm_precision precision, const void *adjoint, void *grad_p,
+                                      void *stream);
+
+/*
+ * Jacobian-vector product (directional derivative) of the assembled RHS:
+ *   drhs = (d rhs / d u) du + (d rhs / d p) dp,
+ * recomputing the element quantities; the eddy viscosity is differentiated as
+ * stated at nsasm_params.  This is the product a Jacobian-free Newton-Krylov
+ * solver of an implicit momentum step needs.
+ * u, du : device, n_nodes x 3, mesh order.   dp : device, n_nodes, or NULL (0).
+ * drhs  : device, n_nodes x 3, mesh order; overwritten (or added to with
+ *         NSASM_ACCUMULATE).  Must not overlap the inputs.
+ * Errors and ordering as nsasm_assemble_rhs.
+ */
+nsasm_status nsasm_assemble_rhs_jvp(const nsasm_mesh *mesh, const nsasm_params *params,
+                                    nsasm_precision precision, const void *u, const void *du,
+                                    const void *dp, void *drhs, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nsasm_last_error(void);
 

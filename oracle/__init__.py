@@ -53,9 +53,10 @@ def _load():
     ci = ctypes.c_int
     lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, ci, dp]
     lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
-    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, d, d, d, dp, ci, dp, dp]
+    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, dp, d, d, d, dp, ci, dp, dp]
     lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
-    for fn in ("oracle_geometry", "oracle_eddy", "oracle_rhs", "oracle_rhs_complex", "oracle_vjp"):
+    lib.oracle_vjp_p.argtypes = [i64, dp, i64, ip, dp, dp, ci]
+    for fn in ("oracle_geometry", "oracle_eddy", "oracle_rhs", "oracle_rhs_complex", "oracle_vjp", "oracle_vjp_p"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -136,16 +137,39 @@ def rhs(coords, conn, u, p, prm: Params, nthreads: int = 0):
 
 
 def rhs_complex(coords, conn, u, p, prm: Params):
-    """RHS for a complex velocity field (complex-step differentiation)."""
+    """RHS for complex velocity and pressure fields (complex-step
+    differentiation)."""
     x, c = _f64(coords), _i32(conn)
     nn = x.shape[0]
     u = np.asarray(u, dtype=np.complex128).reshape(nn, 3)
+    p = np.asarray(p, dtype=np.complex128).reshape(nn)
     ur, ui = _f64(u.real), _f64(u.imag)
-    pp = _f64(p, (nn,))
+    pr, pi = _f64(p.real), _f64(p.imag)
     rr, ri = np.empty((nn, 3)), np.empty((nn, 3))
     _check(_load().oracle_rhs_complex(nn, _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(ur),
-                                      _ptr(ui), _ptr(pp), *prm.args(), _ptr(rr), _ptr(ri)))
+                                      _ptr(ui), _ptr(pr), _ptr(pi), *prm.args(), _ptr(rr), _ptr(ri)))
     return rr + 1j * ri
+
+
+def jvp(coords, conn, u, p, du, dp, prm: Params, h: float = 1e-30):
+    """Directional derivative (dR/du) du + (dR/dp) dp by complex-step
+    differentiation of the oracle: Im R(u + i h du, p + i h dp) / h."""
+    nn = np.asarray(coords).shape[0]
+    u, du = _f64(u, (nn, 3)), _f64(du, (nn, 3))
+    p = _f64(p, (nn,))
+    dp = np.zeros(nn) if dp is None else _f64(dp, (nn,))
+    return rhs_complex(coords, conn, u + 1j * h * du, p + 1j * h * dp, prm).imag / h
+
+
+def vjp_p(coords, conn, lam, nthreads: int = 0):
+    """Pressure VJP (dR/dp)^T lam, shape (Nn,)."""
+    x, c = _f64(coords), _i32(conn)
+    nn = x.shape[0]
+    ll = _f64(lam, (nn, 3))
+    out = np.empty(nn)
+    _check(_load().oracle_vjp_p(nn, _ptr(x), c.shape[0], _ptr(c, ctypes.c_int32), _ptr(ll), _ptr(out),
+                                int(nthreads)))
+    return out
 
 
 def vjp(coords, conn, u, lam, prm: Params, nthreads: int = 0):
@@ -159,17 +183,21 @@ def vjp(coords, conn, u, lam, prm: Params, nthreads: int = 0):
     return out
 
 
-def dense_jacobian_complex_step(coords, conn, u, p, prm: Params, h: float = 1e-30):
-    """dR/du as a dense (3 Nn, 3 Nn) matrix by complex-step differentiation
-    (Squire & Trapp 1998): column k = Im R(u + i h e_k) / h, free of
-    subtractive cancellation."""
+def dense_jacobian_complex_step(coords, conn, u, p, prm: Params, h: float = 1e-30, wrt: str = "u"):
+    """dR/du (3 Nn x 3 Nn) or dR/dp (3 Nn x Nn) as a dense matrix by
+    complex-step differentiation (Squire & Trapp 1998): column k =
+    Im R(v + i h e_k) / h, free of subtractive cancellation."""
     nn = np.asarray(coords).shape[0]
-    u = _f64(u, (nn, 3))
-    jac = np.empty((3 * nn, 3 * nn))
-    for k in range(3 * nn):
-        du = np.zeros(3 * nn)
-        du[k] = h
-        r = rhs_complex(coords, conn, u + 1j * du.reshape(nn, 3), p, prm)
+    u, p = _f64(u, (nn, 3)), _f64(p, (nn,))
+    ncol = 3 * nn if wrt == "u" else nn
+    jac = np.empty((3 * nn, ncol))
+    for k in range(ncol):
+        e = np.zeros(ncol)
+        e[k] = h
+        if wrt == "u":
+            r = rhs_complex(coords, conn, u + 1j * e.reshape(nn, 3), p, prm)
+        else:
+            r = rhs_complex(coords, conn, u, p + 1j * e, prm)
         jac[:, k] = r.imag.reshape(-1) / h
     return jac
 

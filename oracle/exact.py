@@ -121,3 +121,36 @@ def assemble_vjp(coords, conn, u, lam, rho, mu, f):
                 um[b][k] -= 1
                 out[ids[b]][k] += (functional(up) - functional(um)) / 2
     return out
+
+
+def assemble_vjp_p(coords, conn, u, lam, rho, mu, f):
+    """Exact (dR/dp)^T lam: R is affine in p, so a unit step in p_b changes
+    lam . R by exactly the derivative."""
+    nn = len(coords)
+    out = [Fraction(0)] * nn
+    for tet in conn:
+        ids = [int(t) for t in tet]
+        xe = [coords[n] for n in ids]
+        ue = [u[n] for n in ids]
+        le = [lam[n] for n in ids]
+        zero = [Fraction(0)] * 4
+        base = element_rhs(xe, ue, zero, rho, mu, f)
+        for b in range(4):
+            pe = [Fraction(0)] * 4
+            pe[b] = Fraction(1)
+            re = element_rhs(xe, ue, pe, rho, mu, f)
+            out[ids[b]] += sum(le[a][i] * (re[a][i] - base[a][i]) for a in range(4) for i in range(3))
+    return out
+
+
+def assemble_jvp(coords, conn, u, p, du, dp, rho, mu, f):
+    """Exact (dR/du) du + (dR/dp) dp for mu_t = 0: R is quadratic in u and
+    affine in p, so the unit-step central difference is exact."""
+    nn = len(coords)
+    plus = [[u[n][i] + du[n][i] for i in range(3)] for n in range(nn)]
+    minus = [[u[n][i] - du[n][i] for i in range(3)] for n in range(nn)]
+    pp = [p[n] + dp[n] for n in range(nn)]
+    pm = [p[n] - dp[n] for n in range(nn)]
+    rp = assemble_rhs(coords, conn, plus, pp, rho, mu, f)
+    rm = assemble_rhs(coords, conn, minus, pm, rho, mu, f)
+    return [[(rp[n][i] - rm[n][i]) / 2 for i in range(3)] for n in range(nn)]

@@ -285,18 +285,20 @@ int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, con
     return status;
 }
 
-/* Complex-step form: velocity u_re + i u_im, real x and p; serial. */
+/* Complex-step form: velocity u_re + i u_im and pressure p_re + i p_im, real x;
+ * serial. */
 int oracle_rhs_complex(int64_t nn, const double *x, int64_t ne, const int32_t *conn,
-                       const double *u_re, const double *u_im, const double *p, double rho,
-                       double mu, double cs, const double *f, int model, double *r_re, double *r_im) {
+                       const double *u_re, const double *u_im, const double *p_re, const double *p_im,
+                       double rho, double mu, double cs, const double *f, int model, double *r_re,
+                       double *r_im) {
     oracle_params prm;
     set_params(&prm, rho, mu, cs, f, model);
     double complex *acc = (double complex *)calloc((size_t)nn * 3, sizeof(double complex));
     if (!acc) return ORACLE_NOMEM;
     for (int64_t e = 0; e < ne; ++e) {
         int32_t ids[4];
-        double xe[4][3], gN[4][3], V, D, pe[4];
-        double complex ue[4][3], re[4][3];
+        double xe[4][3], gN[4][3], V, D;
+        double complex ue[4][3], pe[4], re[4][3];
         if (!gather_element(nn, x, conn, e, ids, xe)) { free(acc); return ORACLE_BAD_INDEX; }
         if (!element_geometry(xe, gN, &V, &D)) { free(acc); return ORACLE_DEGENERATE; }
         for (int a = 0; a < 4; ++a) {
@@ -304,7 +306,7 @@ int oracle_rhs_complex(int64_t nn, const double *x, int64_t ne, const int32_t *c
                 int64_t k = 3 * (int64_t)ids[a] + i;
                 ue[a][i] = u_re[k] + I * u_im[k];
             }
-            pe[a] = p[ids[a]];
+            pe[a] = p_re[ids[a]] + I * p_im[ids[a]];
         }
         element_rhs_c(gN, V, ue, pe, &prm, re);
         for (int a = 0; a < 4; ++a)
@@ -422,6 +424,64 @@ int oracle_vjp(int64_t nn, const double *x, int64_t ne, const int32_t *conn, con
             double s = 0;
             for (int tt = 0; tt < nt; ++tt) s += part[(size_t)tt * (size_t)nn * 3 + k];
             grad[k] = s;
+        }
+    }
+    free(part);
+    return status;
+}
+
+/* Pressure vector-Jacobian product g_p = (dR/dp)^T lam (nn values).  The
+ * pressure enters only through -sum_g (V/4) N_a(g) q with q = grad p, so per
+ * element g_p[b] = -sum_g (V/4) lambda^g . grad N_b.  OpenMP as oracle_rhs. */
+int oracle_vjp_p(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *lam,
+                 double *grad_p, int nthreads) {
+    const int nt = n_threads_or_default(nthreads);
+    double *part = (double *)calloc((size_t)nt * (size_t)nn, sizeof(double));
+    if (!part) return ORACLE_NOMEM;
+    int status = ORACLE_OK;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        const int t = omp_get_thread_num();
+#else
+        const int t = 0;
+#endif
+        double *mine = part + (size_t)t * (size_t)nn;
+#pragma omp for schedule(static)
+        for (int64_t e = 0; e < ne; ++e) {
+            int32_t ids[4];
+            double xe[4][3], gN[4][3], V, D, le[4][3];
+            if (!gather_element(nn, x, conn, e, ids, xe)) {
+#pragma omp atomic write
+                status = ORACLE_BAD_INDEX;
+                continue;
+            }
+            if (!element_geometry(xe, gN, &V, &D)) {
+#pragma omp atomic write
+                status = ORACLE_DEGENERATE;
+                continue;
+            }
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) le[a][i] = lam[3 * (int64_t)ids[a] + i];
+            for (int g = 0; g < 4; ++g) {
+                double N[4], lg[3];
+                for (int a = 0; a < 4; ++a) N[a] = (a == g) ? GAUSS_ALPHA : GAUSS_BETA;
+                for (int i = 0; i < 3; ++i) {
+                    lg[i] = 0;
+                    for (int a = 0; a < 4; ++a) lg[i] += N[a] * le[a][i];
+                }
+                for (int b = 0; b < 4; ++b) {
+                    double dot = 0;
+                    for (int i = 0; i < 3; ++i) dot += lg[i] * gN[b][i];
+                    mine[ids[b]] -= (V / 4.0) * dot;
+                }
+            }
+        }
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < nn; ++k) {
+            double s = 0;
+            for (int tt = 0; tt < nt; ++tt) s += part[(size_t)tt * (size_t)nn + k];
+            grad_p[k] = s;
         }
     }
     free(part);

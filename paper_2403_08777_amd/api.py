@@ -64,9 +64,12 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_from_mesh_order.argtypes = [vp, i32, st, vp, vp, vp]
     lib.nsasm_assemble_rhs.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
     lib.nsasm_assemble_rhs_vjp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
+    lib.nsasm_assemble_rhs_vjp_p.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp]
+    lib.nsasm_assemble_rhs_jvp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp, vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
-                 "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp"):
+                 "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp", "nsasm_assemble_rhs_vjp_p",
+                 "nsasm_assemble_rhs_jvp"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -240,24 +243,68 @@ def assemble_rhs_vjp(mesh: Mesh, u: torch.Tensor, adjoint: torch.Tensor, params:
     return out
 
 
+def assemble_rhs_vjp_p(mesh: Mesh, adjoint: torch.Tensor, params: Params, out: torch.Tensor = None,
+                       accumulate: bool = False, stream=None) -> torch.Tensor:
+    """(d rhs / d p)^T adjoint, (Nn,) in mesh order."""
+    prec = _precision_of(adjoint)
+    nn = mesh.n_nodes
+    _dev(adjoint, adjoint.dtype, (nn, 3), "adjoint")
+    if out is None:
+        out = torch.empty(nn, dtype=adjoint.dtype, device=adjoint.device)
+    else:
+        _dev(out, adjoint.dtype, (nn,), "out")
+    prm = params.c_struct(accumulate)
+    _check(lib.nsasm_assemble_rhs_vjp_p(mesh.handle, ctypes.byref(prm), prec, adjoint.data_ptr(), out.data_ptr(),
+                                        _stream(stream)))
+    return out
+
+
+def assemble_rhs_jvp(mesh: Mesh, u: torch.Tensor, du: torch.Tensor, dp: torch.Tensor, params: Params,
+                     out: torch.Tensor = None, accumulate: bool = False, stream=None) -> torch.Tensor:
+    """(d rhs / d u) du + (d rhs / d p) dp, (Nn, 3) in mesh order; dp may be None."""
+    prec = _precision_of(u)
+    nn = mesh.n_nodes
+    _dev(u, u.dtype, (nn, 3), "u")
+    _dev(du, u.dtype, (nn, 3), "du")
+    if dp is not None:
+        _dev(dp, u.dtype, (nn,), "dp")
+    if out is None:
+        out = torch.empty((nn, 3), dtype=u.dtype, device=u.device)
+    else:
+        _dev(out, u.dtype, (nn, 3), "out")
+    prm = params.c_struct(accumulate)
+    _check(lib.nsasm_assemble_rhs_jvp(mesh.handle, ctypes.byref(prm), prec, u.data_ptr(), du.data_ptr(),
+                                      None if dp is None else dp.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
 class NSAssembleRHS(torch.autograd.Function):
-    """rhs = NSAssembleRHS.apply(u, p, mesh, params); differentiable in u.
-    The backward pass calls the hand-written VJP kernel, recomputing element
-    quantities instead of storing them."""
+    """rhs = NSAssembleRHS.apply(u, p, mesh, params); differentiable in u and p,
+    in reverse mode (hand-written VJP kernels) and forward mode (the JVP
+    kernel).  Element quantities are recomputed, never stored."""
 
     @staticmethod
     def forward(ctx, u, p, mesh, params):
-        if p.requires_grad:
-            raise NotImplementedError("the pressure VJP is not provided; detach p")
         ctx.mesh, ctx.params = mesh, params
+        u, p = u.contiguous(), p.contiguous()
         ctx.save_for_backward(u)
-        return assemble_rhs(mesh, u.contiguous(), p.contiguous(), params)
+        ctx.save_for_forward(u)
+        return assemble_rhs(mesh, u, p, params)
 
     @staticmethod
     def backward(ctx, grad_rhs):
         (u,) = ctx.saved_tensors
-        g = assemble_rhs_vjp(ctx.mesh, u.contiguous(), grad_rhs.contiguous(), ctx.params)
-        return g, None, None, None
+        lam = grad_rhs.contiguous()
+        gu = assemble_rhs_vjp(ctx.mesh, u, lam, ctx.params) if ctx.needs_input_grad[0] else None
+        gp = assemble_rhs_vjp_p(ctx.mesh, lam, ctx.params) if ctx.needs_input_grad[1] else None
+        return gu, gp, None, None
+
+    @staticmethod
+    def jvp(ctx, du, dp, _mesh_t, _params_t):
+        (u,) = ctx.saved_tensors
+        if du is None:
+            du = torch.zeros_like(u)
+        return assemble_rhs_jvp(ctx.mesh, u, du.contiguous(), None if dp is None else dp.contiguous(), ctx.params)
 
 
 def version() -> str:

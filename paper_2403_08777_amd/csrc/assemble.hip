@@ -47,7 +47,20 @@ namespace nsasm {
 namespace {
 
 constexpr int kThreads = 256;
-enum Mode { kForward = 0, kVjp = 1 };
+// What a launch computes.  Node fields: A (vector), B (vector), C (scalar).
+//   kForward: A = u, C = p            -> rhs (3 per node)
+//   kVjp:     A = u, B = adjoint      -> (d rhs / d u)^T adjoint (3)
+//   kVjpP:    B = adjoint             -> (d rhs / d p)^T adjoint (1)
+//   kJvp:     A = u, B = du, C = dp   -> (d rhs / d u) du + (d rhs / d p) dp (3)
+enum Mode { kForward = 0, kVjp = 1, kVjpP = 2, kJvp = 3 };
+
+template <int MODE>
+struct Fields {
+    static constexpr int NA = (MODE == kVjpP) ? 0 : 3;
+    static constexpr int NB = (MODE == kForward) ? 0 : 3;
+    static constexpr int NC = (MODE == kForward || MODE == kJvp) ? 1 : 0;
+    static constexpr int NOUT = (MODE == kVjpP) ? 1 : 3;
+};
 
 template <typename T>
 struct KParams {
@@ -251,6 +264,76 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
     }
 }
 
+// Pressure VJP: the pressure term -(V/4) q at every vertex is linear in p,
+// so lambda . R^p = -(V/4) L . q with L = sum_a lambda_a and
+// d/dp_b = -(V/4) L . grad N_b.
+template <typename T>
+__device__ inline void element_vjp_p(const T (&gN)[4][3], T vol, const T (&le)[4][3], T (&gp)[4][3]) {
+    const T w = -vol * T(0.25);
+    T L[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L[i] = le[0][i] + le[1][i] + le[2][i] + le[3][i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gp[b][0] = w * (L[0] * gN[b][0] + L[1] * gN[b][1] + L[2] * gN[b][2]);
+}
+
+// JVP: directional derivative of R^e_a = b - G y_a along (du, dp):
+//   dR^e_a = -(V/4) dq - dG y_a - G dy_a,
+//   dy_a = (rho V / 20)(du_a + dU) + V (D : dG) grad N_a,
+// with dG = grad du, dq = grad dp and D = d mu_t / d G.
+template <typename T, int EDDY>
+__device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&due)[4][3],
+                                   const T (&dpe)[4], const KParams<T> &P, T (&dr)[4][3]) {
+    T G[3][3], dG[3][3], dq[3];
+    vector_gradient(gN, ue, G);
+    vector_gradient(gN, due, dG);
+    {
+        const T d1 = dpe[1] - dpe[0], d2 = dpe[2] - dpe[0], d3 = dpe[3] - dpe[0];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) dq[j] = d1 * gN[1][j] + d2 * gN[2][j] + d3 * gN[3][j];
+    }
+    T D[3][3];
+    const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
+    T dmu = T(0);
+    if (EDDY != kNoEddy) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dmu += D[i][j] * dG[i][j];
+    }
+    const T sc = P.rho * vol * T(0.05);
+    const T sv = mu_e * vol, dsv = dmu * vol, w4 = vol * T(0.25);
+    T U[3], dU[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
+        dU[i] = due[0][i] + due[1][i] + due[2][i] + due[3][i];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        T y[3], dy[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            y[j] = sc * (ue[a][j] + U[j]) + sv * gN[a][j];
+            dy[j] = sc * (due[a][j] + dU[j]) + dsv * gN[a][j];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            dr[a][i] = -w4 * dq[i] - (dG[i][0] * y[0] + dG[i][1] * y[1] + dG[i][2] * y[2]) -
+                       (G[i][0] * dy[0] + G[i][1] * dy[1] + G[i][2] * dy[2]);
+    }
+}
+
+// The element operation of a launch mode on gathered vertex data.
+template <typename T, int EDDY, int MODE>
+__device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3], const T (&eb)[4][3],
+                                  const T (&ec)[4], const KParams<T> &P, T (&r)[4][3]) {
+    if (MODE == kForward) element_rhs<T, EDDY>(gN, vol, ea, ec, P, r);
+    if (MODE == kVjp) element_vjp<T, EDDY>(gN, vol, ea, eb, P, r);
+    if (MODE == kVjpP) element_vjp_p(gN, vol, eb, r);
+    if (MODE == kJvp) element_jvp<T, EDDY>(gN, vol, ea, eb, ec, P, r);
+}
+
 template <typename T>
 __device__ inline void to_field(const double (&g64)[4][3], double vol64, T (&gN)[4][3], T &vol) {
 #pragma unroll
@@ -269,49 +352,47 @@ __global__ __launch_bounds__(kThreads) void k_fill_zero(T *p, int64_t n) {
         p[k] = T(0);
 }
 
-// One thread per element; f0 = u, f1 = p (forward) or lambda (VJP).
+// Node fields of a launch (see Mode); fc may be null (read as 0).
+template <typename T>
+struct NodeFields {
+    const T *fa;
+    const T *fb;
+    const T *fc;
+};
+
+// One thread per element, NOUT global atomic adds per vertex.
 template <typename T, int EDDY, int MODE>
 __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const int4 *__restrict__ conn,
-                                                               const double *__restrict__ x,
-                                                               const T *__restrict__ f0,
-                                                               const T *__restrict__ f1, KParams<T> P,
-                                                               T *__restrict__ out) {
+                                                               const double *__restrict__ x, NodeFields<T> F,
+                                                               KParams<T> P, T *__restrict__ out) {
+    using FL = Fields<MODE>;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t e = tile * kThreads + threadIdx.x;
     if (e >= ne) return;
     const int4 c = conn[e];
     const int64_t ids[4] = {c.x, c.y, c.z, c.w};
     double xe[4][3];
-    T ue[4][3];
+    T ea[4][3] = {}, eb[4][3] = {}, ec[4] = {};
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             xe[a][i] = x[3 * ids[a] + i];
-            ue[a][i] = f0[3 * ids[a] + i];
+            if (FL::NA) ea[a][i] = F.fa[3 * ids[a] + i];
+            if (FL::NB) eb[a][i] = F.fb[3 * ids[a] + i];
         }
+        if (FL::NC) ec[a] = F.fc ? F.fc[ids[a]] : T(0);
+    }
     double g64[4][3], vol64;
     tet_geometry(xe, g64, vol64);
     T gN[4][3], vol;
     to_field(g64, vol64, gN, vol);
     T r[4][3];
-    if (MODE == kForward) {
-        T pe[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) pe[a] = f1[ids[a]];
-        element_rhs<T, EDDY>(gN, vol, ue, pe, P, r);
-    } else {
-        T le[4][3];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) le[a][i] = f1[3 * ids[a] + i];
-        element_vjp<T, EDDY>(gN, vol, ue, le, P, r);
-    }
+    element_op<T, EDDY, MODE>(gN, vol, ea, eb, ec, P, r);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) global_add(&out[3 * ids[a] + i], r[a][i]);
+        for (int i = 0; i < FL::NOUT; ++i) global_add(&out[FL::NOUT * ids[a] + i], r[a][i]);
 }
 
 // One workgroup per patch (see the file header).  LDS holds the patch's
@@ -326,16 +407,16 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, const int32_t *__restrict__ patch_off,
     const int32_t *__restrict__ patch_nodes, const int32_t *__restrict__ patch_node_start,
     const int32_t *__restrict__ ref_slot, const ushort4 *__restrict__ elem_pos, const double *__restrict__ x,
-    const T *__restrict__ f0, const T *__restrict__ f1, KParams<T> P, T *__restrict__ out) {
-    constexpr int kF1 = (MODE == kForward) ? 1 : 3;
+    NodeFields<T> F, KParams<T> P, T *__restrict__ out) {
+    using FL = Fields<MODE>;
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
-    constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + (3 + kF1) * kN * sizeof(T);
-    constexpr size_t kSlotBytes = 3 * kS * sizeof(T);
+    constexpr int kNF = FL::NA + FL::NB + FL::NC;
+    constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
+    constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     __shared__ uint8_t node_of_slot[kS];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
-    T(*su)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));
-    T(*s1)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double) + 3 * kN * sizeof(T));
+    T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
     T(*sval)[kS] = reinterpret_cast<T(*)[kS]>(smem);
 
     const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
@@ -357,10 +438,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             sx[i][t] = x[3 * node + i];
-            su[i][t] = f0[3 * node + i];
+            if (FL::NA) sf[i][t] = F.fa[3 * node + i];
+            if (FL::NB) sf[FL::NA + i][t] = F.fb[3 * node + i];
         }
-#pragma unroll
-        for (int i = 0; i < kF1; ++i) s1[i][t] = f1[kF1 * node + i];
+        if (FL::NC) sf[FL::NA + FL::NB][t] = F.fc ? F.fc[node] : T(0);
         for (int k = s_beg; k < s_end; ++k) node_of_slot[k] = static_cast<uint8_t>(t);
     }
     __syncthreads();
@@ -372,70 +453,65 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
         for (int a = 0; a < 4; ++a) la[a] = node_of_slot[sl[a]];
         double xe[4][3];
-        T ue[4][3];
+        T ea[4][3] = {}, eb[4][3] = {}, ec[4] = {};
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 xe[a][i] = sx[i][la[a]];
-                ue[a][i] = su[i][la[a]];
+                if (FL::NA) ea[a][i] = sf[i][la[a]];
+                if (FL::NB) eb[a][i] = sf[FL::NA + i][la[a]];
             }
+            if (FL::NC) ec[a] = sf[FL::NA + FL::NB][la[a]];
+        }
         double g64[4][3], vol64;
         tet_geometry(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
-        if (MODE == kForward) {
-            T pe[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) pe[a] = s1[0][la[a]];
-            element_rhs<T, EDDY>(gN, vol, ue, pe, P, r);
-        } else {
-            T le[4][3];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) le[a][i] = s1[i][la[a]];
-            element_vjp<T, EDDY>(gN, vol, ue, le, P, r);
-        }
+        element_op<T, EDDY, MODE>(gN, vol, ea, eb, ec, P, r);
     }
     __syncthreads();  // node data is dead from here on; its bytes become slots
     if (t < nel) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) sval[i][sl[a]] = r[a][i];
+            for (int i = 0; i < FL::NOUT; ++i) sval[i][sl[a]] = r[a][i];
     }
     __syncthreads();
     if (t < cnt) {
-        T acc[3] = {T(0), T(0), T(0)};
+        T acc[FL::NOUT];
+#pragma unroll
+        for (int i = 0; i < FL::NOUT; ++i) acc[i] = T(0);
         for (int k = s_beg; k < s_end; ++k)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) acc[i] += sval[i][k];
+            for (int i = 0; i < FL::NOUT; ++i) acc[i] += sval[i][k];
         if (GATHER) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) out[3 * static_cast<int64_t>(slot) + i] = acc[i];
+            for (int i = 0; i < FL::NOUT; ++i) out[FL::NOUT * static_cast<int64_t>(slot) + i] = acc[i];
         } else {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) global_add(&out[3 * node + i], acc[i]);
+            for (int i = 0; i < FL::NOUT; ++i) global_add(&out[FL::NOUT * node + i], acc[i]);
         }
     }
 }
 
 // out[n] (+)= sum of node n's patch partial sums, which are stored
 // contiguously (node-major, patch order) at [ref_off[n], ref_off[n+1]).
-template <typename T>
+template <typename T, int NOUT>
 __global__ __launch_bounds__(kThreads) void k_gather_partials(int64_t nn, const int32_t *__restrict__ ref_off,
                                                                const T *__restrict__ partial, T *__restrict__ out,
                                                                int accumulate) {
     const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
     if (n >= nn) return;
-    T acc[3] = {T(0), T(0), T(0)};
+    T acc[NOUT];
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
     const int64_t kb = ref_off[n], ke = ref_off[n + 1];
     for (int64_t k = kb; k < ke; ++k)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) acc[i] += partial[3 * k + i];
+        for (int i = 0; i < NOUT; ++i) acc[i] += partial[NOUT * k + i];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) out[3 * n + i] = accumulate ? out[3 * n + i] + acc[i] : acc[i];
+    for (int i = 0; i < NOUT; ++i) out[NOUT * n + i] = accumulate ? out[NOUT * n + i] + acc[i] : acc[i];
 }
 
 // ---------------------------------------------------------- host side
@@ -472,36 +548,37 @@ KParams<T> kernel_params(const nsasm_params &p) {
 }
 
 template <typename T, int EDDY, int MODE>
-nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, const T *f0, const T *f1, T *out,
-                    bool accumulate, hipStream_t s) {
+nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, T *out, bool accumulate,
+                    hipStream_t s) {
+    constexpr int NOUT = Fields<MODE>::NOUT;
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
         T *partial = reinterpret_cast<T *>(m->partial);
         k_assemble_patch<T, EDDY, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
             m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
-            m->ref_slot, m->elem_pos, m->x, f0, f1, kp, partial);
+            m->ref_slot, m->elem_pos, m->x, F, kp, partial);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
         const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
-        k_gather_partials<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial, out,
-                                                                  accumulate ? 1 : 0);
+        k_gather_partials<T, NOUT><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial, out,
+                                                                        accumulate ? 1 : 0);
     } else if (m->scatter == NSASM_SCATTER_PATCH) {
         k_assemble_patch<T, EDDY, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
             m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
-            m->ref_slot, m->elem_pos, m->x, f0, f1, kp, out);
+            m->ref_slot, m->elem_pos, m->x, F, kp, out);
     } else {
         const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
-        k_assemble_atomic<T, EDDY, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x,
-                                                                             f0, f1, kp, out);
+        k_assemble_atomic<T, EDDY, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x, F, kp,
+                                                                             out);
     }
     hipError_t err = hipGetLastError();
     return err == hipSuccess ? NSASM_OK : hip_fail(err, "assembly kernel launch");
 }
 
 template <typename T, int MODE>
-nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, const void *f1, void *out,
-                 hipStream_t s) {
+nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *fa, const void *fb, const void *fc,
+                 void *out, hipStream_t s) {
     T *o = static_cast<T *>(out);
-    const int64_t n_out = 3 * m->n_nodes;
+    const int64_t n_out = Fields<MODE>::NOUT * m->n_nodes;
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     // the gather kernel writes every node, so it needs no zero-fill
     if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER) {
@@ -511,37 +588,47 @@ nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *f0, con
         if (err != hipSuccess) return hip_fail(err, "fill kernel launch");
     }
     const KParams<T> kp = kernel_params<T>(p);
-    const T *a = static_cast<const T *>(f0), *b = static_cast<const T *>(f1);
-    if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
-        return launch<T, kVreman, MODE>(m, kp, a, b, o, accumulate, s);
-    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, MODE>(m, kp, a, b, o, accumulate, s);
-    return launch<T, kNoEddy, MODE>(m, kp, a, b, o, accumulate, s);
+    const NodeFields<T> F{static_cast<const T *>(fa), static_cast<const T *>(fb), static_cast<const T *>(fc)};
+    if constexpr (MODE == kVjpP) {
+        return launch<T, kNoEddy, MODE>(m, kp, F, o, accumulate, s);  // the pressure term has no viscosity
+    } else {
+        if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
+            return launch<T, kVreman, MODE>(m, kp, F, o, accumulate, s);
+        if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, MODE>(m, kp, F, o, accumulate, s);
+        return launch<T, kNoEddy, MODE>(m, kp, F, o, accumulate, s);
+    }
 }
 
-nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, const void *f0,
-                   const void *f1, void *out, void *stream, int mode) {
+// One device array argument of an entry point: name, pointer, components per
+// node (0: not used by the mode), whether NULL is allowed.
+struct Arg {
+    const char *name;
+    const void *ptr;
+    int ncomp;
+    bool nullable;
+};
+
+template <int MODE>
+nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, Arg a, Arg b, Arg c,
+                   Arg out, void *stream) {
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
     if (prec != NSASM_FP64 && prec != NSASM_MIXED)
         return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown precision %d", static_cast<int>(prec));
-    const char *n1 = (mode == kForward) ? "p" : "adjoint";
-    const char *no = (mode == kForward) ? "rhs" : "grad_u";
-    NSASM_TRY(check_device_ptr(f0, "u"));
-    NSASM_TRY(check_device_ptr(f1, n1));
-    NSASM_TRY(check_device_ptr(out, no));
     const size_t es = (prec == NSASM_FP64) ? sizeof(double) : sizeof(float);
-    const size_t n3 = 3 * static_cast<size_t>(m->n_nodes) * es;
-    const size_t n1b = ((mode == kForward) ? 1 : 3) * static_cast<size_t>(m->n_nodes) * es;
-    if (overlaps(out, n3, f0, n3) || overlaps(out, n3, f1, n1b))
-        return fail(NSASM_ERR_INVALID_ARGUMENT, "%s overlaps an input", no);
+    const Arg inputs[3] = {a, b, c};
+    NSASM_TRY(check_device_ptr(out.ptr, out.name));
+    const size_t out_bytes = static_cast<size_t>(out.ncomp) * m->n_nodes * es;
+    for (const Arg &in : inputs) {
+        if (in.ncomp == 0 || (in.nullable && in.ptr == nullptr)) continue;
+        NSASM_TRY(check_device_ptr(in.ptr, in.name));
+        if (overlaps(out.ptr, out_bytes, in.ptr, static_cast<size_t>(in.ncomp) * m->n_nodes * es))
+            return fail(NSASM_ERR_INVALID_ARGUMENT, "%s overlaps %s", out.name, in.name);
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    nsasm_status st;
-    if (prec == NSASM_FP64)
-        st = (mode == kForward) ? run<double, kForward>(m, *params, f0, f1, out, s)
-                                : run<double, kVjp>(m, *params, f0, f1, out, s);
-    else
-        st = (mode == kForward) ? run<float, kForward>(m, *params, f0, f1, out, s)
-                                : run<float, kVjp>(m, *params, f0, f1, out, s);
+    void *o = const_cast<void *>(out.ptr);
+    const nsasm_status st = (prec == NSASM_FP64) ? run<double, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, s)
+                                                 : run<float, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, s);
     if (st == NSASM_OK) clear_error();
     return st;
 }
@@ -552,11 +639,31 @@ nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precis
 extern "C" nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
                                            nsasm_precision precision, const void *u, const void *p,
                                            void *rhs, void *stream) {
-    return nsasm::entry(mesh, params, precision, u, p, rhs, stream, nsasm::kForward);
+    using namespace nsasm;
+    return entry<kForward>(mesh, params, precision, {"u", u, 3, false}, {"unused", nullptr, 0, true},
+                           {"p", p, 1, false}, {"rhs", rhs, 3, false}, stream);
 }
 
 extern "C" nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *params,
                                                nsasm_precision precision, const void *u,
                                                const void *adjoint, void *grad_u, void *stream) {
-    return nsasm::entry(mesh, params, precision, u, adjoint, grad_u, stream, nsasm::kVjp);
+    using namespace nsasm;
+    return entry<kVjp>(mesh, params, precision, {"u", u, 3, false}, {"adjoint", adjoint, 3, false},
+                       {"unused", nullptr, 0, true}, {"grad_u", grad_u, 3, false}, stream);
+}
+
+extern "C" nsasm_status nsasm_assemble_rhs_vjp_p(const nsasm_mesh *mesh, const nsasm_params *params,
+                                                 nsasm_precision precision, const void *adjoint, void *grad_p,
+                                                 void *stream) {
+    using namespace nsasm;
+    return entry<kVjpP>(mesh, params, precision, {"unused", nullptr, 0, true}, {"adjoint", adjoint, 3, false},
+                        {"unused", nullptr, 0, true}, {"grad_p", grad_p, 1, false}, stream);
+}
+
+extern "C" nsasm_status nsasm_assemble_rhs_jvp(const nsasm_mesh *mesh, const nsasm_params *params,
+                                               nsasm_precision precision, const void *u, const void *du,
+                                               const void *dp, void *drhs, void *stream) {
+    using namespace nsasm;
+    return entry<kJvp>(mesh, params, precision, {"u", u, 3, false}, {"du", du, 3, false}, {"dp", dp, 1, true},
+                       {"drhs", drhs, 3, false}, stream);
 }

@@ -100,3 +100,21 @@ def test_vreman_full_160():
     eg = oracle.rel_l2(g, oracle.vjp(m.coords, m.conn, u, lam, oprm))
     log(f"cube160 vreman fp64 rel_l2: rhs {er:.3e}, grad {eg:.3e}")
     assert er <= 1e-12 and eg <= 1e-12
+
+
+def test_jvp_duality_full_96():
+    """At full size: lambda . (J v) from the GPU JVP equals (J^T lambda) . v
+    from the oracle's velocity and pressure VJPs (an identity at any size)."""
+    from paper_2403_08777_amd import api
+
+    wl, m, u, p, lam, mesh = _case("cube96_jit_perm")
+    prm, oprm = _params(wl)
+    rng = np.random.default_rng(13)
+    du, dp = rng.standard_normal(u.shape), rng.standard_normal(p.shape)
+    dev = torch.device("cuda")
+    tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    jv = mesh.from_mesh_order(api.assemble_rhs_jvp(mesh, tm(u), tm(du), tm(dp), prm)).cpu().numpy()
+    lhs = float(np.sum(lam * jv))
+    rhs = float(np.sum(oracle.vjp(m.coords, m.conn, u, lam, oprm) * du) + np.sum(oracle.vjp_p(m.coords, m.conn, lam) * dp))
+    log(f"cube96 jvp duality: {lhs:.15e} vs {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)

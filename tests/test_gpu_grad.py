@@ -67,5 +67,84 @@ def test_autograd_backward_matches_vjp():
     (rhs * lam).sum().backward()
     g = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
     assert oracle.rel_l2(uu.grad.cpu().numpy(), g.cpu().numpy()) <= 1e-14
-    with pytest.raises(NotImplementedError):
-        api.NSAssembleRHS.apply(uu, p.clone().requires_grad_(True), pr.mesh, case.params())
+
+
+JVP_CASES = [Case(2, jitter=True, permute=True, mu=1e-3),
+             Case(4, jitter=True, permute=True, mu=1e-4, cs=0.1),
+             Case(7, jitter=True, permute=True, mu=1e-4, cs=0.1, model="vreman"),
+             Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1)]
+
+
+def _dirs(pr):
+    rng = np.random.default_rng(11)
+    return rng.standard_normal(pr.u.shape), rng.standard_normal(pr.p.shape)
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+@pytest.mark.parametrize("case", JVP_CASES, ids=[c.label() for c in JVP_CASES])
+def test_jvp_and_pressure_vjp_fp64(case, scatter):
+    from paper_2403_08777_amd import api
+
+    pr = Prepared(case, scatter=scatter)
+    du, dp = _dirs(pr)
+    dev = pr.dev
+    u, p, lam = pr.fields(torch.float64)
+    to_mesh = lambda a: pr.mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    prm = case.params()
+    got = pr.mesh.from_mesh_order(api.assemble_rhs_jvp(pr.mesh, u, to_mesh(du), to_mesh(dp), prm)).cpu().numpy()
+    ref = oracle.jvp(pr.m.coords, pr.m.conn, pr.u, pr.p, du, dp, case.oracle_params())
+    e1 = oracle.rel_l2(got, ref)
+    got0 = pr.mesh.from_mesh_order(api.assemble_rhs_jvp(pr.mesh, u, to_mesh(du), None, prm)).cpu().numpy()
+    ref0 = oracle.jvp(pr.m.coords, pr.m.conn, pr.u, pr.p, du, None, case.oracle_params())
+    e2 = oracle.rel_l2(got0, ref0)
+    gp = pr.mesh.from_mesh_order(api.assemble_rhs_vjp_p(pr.mesh, lam, prm)).cpu().numpy()
+    e3 = oracle.rel_l2(gp, oracle.vjp_p(pr.m.coords, pr.m.conn, pr.lam))
+    log(f"{case.label()} {scatter}: jvp {e1:.2e}, jvp(dp=0) {e2:.2e}, vjp_p {e3:.2e}")
+    assert e1 <= 1e-12 and e2 <= 1e-12 and e3 <= 1e-12
+
+
+@pytest.mark.parametrize("case", JVP_CASES[1:], ids=[c.label() for c in JVP_CASES[1:]])
+def test_jvp_and_pressure_vjp_mixed(case):
+    from paper_2403_08777_amd import api
+
+    pr = Prepared(case)
+    du, dp = _dirs(pr)
+    dev = pr.dev
+    u, p, lam = pr.fields(torch.float32)
+    to_mesh = lambda a: pr.mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32))
+    prm = case.params()
+    got = pr.mesh.from_mesh_order(api.assemble_rhs_jvp(pr.mesh, u, to_mesh(du), to_mesh(dp), prm))
+    e1 = oracle.rel_l2(got.double().cpu().numpy(),
+                       oracle.jvp(pr.m.coords, pr.m.conn, pr.u, pr.p, du, dp, case.oracle_params()))
+    gp = pr.mesh.from_mesh_order(api.assemble_rhs_vjp_p(pr.mesh, lam, prm))
+    e2 = oracle.rel_l2(gp.double().cpu().numpy(), oracle.vjp_p(pr.m.coords, pr.m.conn, pr.lam))
+    log(f"mixed {case.label()}: jvp {e1:.2e}, vjp_p {e2:.2e}")
+    assert e1 <= 1e-4 and e2 <= 1e-4
+
+
+def test_autograd_pressure_and_forward_mode():
+    import torch.autograd.forward_ad as fwAD
+
+    from paper_2403_08777_amd import api
+
+    case = Case(3, jitter=True, permute=True, mu=1e-2, cs=0.1, model="vreman")
+    pr = Prepared(case)
+    u, p, lam = pr.fields(torch.float64)
+    prm = case.params()
+    uu = u.clone().requires_grad_(True)
+    pp = p.clone().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: api.NSAssembleRHS.apply(a, b, pr.mesh, prm), (uu, pp),
+                                    eps=1e-6, atol=1e-8, rtol=1e-6)
+    # forward mode through dual tensors equals the JVP kernel
+    du = torch.randn_like(u)
+    dp = torch.randn_like(p)
+    with fwAD.dual_level():
+        out = api.NSAssembleRHS.apply(fwAD.make_dual(u, du), fwAD.make_dual(p, dp), pr.mesh, prm)
+        tangent = fwAD.unpack_dual(out).tangent
+    ref = api.assemble_rhs_jvp(pr.mesh, u, du, dp, prm)
+    assert oracle.rel_l2(tangent.cpu().numpy(), ref.cpu().numpy()) <= 1e-15
+    # pressure gradient through backward
+    pp = p.clone().requires_grad_(True)
+    (api.NSAssembleRHS.apply(u, pp, pr.mesh, prm) * lam).sum().backward()
+    gp = api.assemble_rhs_vjp_p(pr.mesh, lam, prm)
+    assert oracle.rel_l2(pp.grad.cpu().numpy(), gp.cpu().numpy()) <= 1e-15

@@ -438,3 +438,53 @@ def test_vreman_vjp_central_fd_16(oracle_lib):
           np.sum(lam * oracle.rhs(m.coords, m.conn, u - h * d, p, prm))) / (2 * h)
     gd = np.sum(oracle.vjp(m.coords, m.conn, u, lam, prm) * d)
     assert abs(fd - gd) <= 1e-6 * abs(gd)
+
+
+# ------------------------------------------------------- pressure VJP and JVP
+
+def test_vjp_p_exact_and_complex_step(oracle_lib):
+    coords, conn, xf = dyadic_mesh(2, 33)
+    rng = np.random.default_rng(34)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    lq, lf = dyadic_field(rng, len(coords), 3)
+    ref = np.array([float(v) for v in exact.assemble_vjp_p(coords, conn, uq, lq, Fraction(1), Fraction(1, 64),
+                                                           [Fraction(0)] * 3)])
+    got = oracle.vjp_p(xf, conn, lf)
+    assert oracle.rel_l2(got, ref) < 1e-14
+    m = synth.cube_mesh(2, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    for model in ("smagorinsky", "vreman"):
+        prm = oracle.Params(1.0, 1e-3, 0.1, F, model=model)
+        jac = oracle.dense_jacobian_complex_step(m.coords, m.conn, u, p, prm, wrt="p")
+        assert oracle.rel_l2(oracle.vjp_p(m.coords, m.conn, lam), jac.T @ lam.reshape(-1)) < 1e-12
+
+
+def test_jvp_exact_rational(oracle_lib):
+    coords, conn, xf = dyadic_mesh(2, 35)
+    rng = np.random.default_rng(36)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    pq, pf = dyadic_field(rng, len(coords), 1)
+    duq, duf = dyadic_field(rng, len(coords), 3)
+    dpq, dpf = dyadic_field(rng, len(coords), 1)
+    pq, dpq = [r[0] for r in pq], [r[0] for r in dpq]
+    rho, mu = Fraction(3, 2), Fraction(1, 64)
+    fq = [Fraction(1, 10), Fraction(-2, 10), Fraction(3, 10)]
+    ref = frac_to_np(exact.assemble_jvp(coords, conn, uq, pq, duq, dpq, rho, mu, fq))
+    got = oracle.jvp(xf, conn, uf, pf[:, 0], duf, dpf[:, 0], oracle.Params(float(rho), float(mu), 0.0, F))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("model", ["smagorinsky", "vreman"])
+def test_jvp_vjp_duality_16(oracle_lib, model):
+    """lambda . (J v) = (J^T lambda) . v with J v by complex step and J^T lambda
+    by the analytic VJPs (velocity and pressure)."""
+    m = synth.cube_mesh(16, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    rng = np.random.default_rng(37)
+    du, dp = rng.standard_normal(u.shape), rng.standard_normal(p.shape)
+    prm = oracle.Params(1.0, 1e-4, 0.1, F, model=model)
+    lhs = np.sum(lam * oracle.jvp(m.coords, m.conn, u, p, du, dp, prm))
+    rhs = np.sum(oracle.vjp(m.coords, m.conn, u, lam, prm) * du) + np.sum(oracle.vjp_p(m.coords, m.conn, lam) * dp)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
