@@ -51,10 +51,10 @@ def _load():
     lib.oracle_default_threads.restype = ctypes.c_int
     lib.oracle_geometry.argtypes = [i64, dp, i64, ip, dp, dp]
     ci = ctypes.c_int
-    lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, ci, dp]
-    lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
-    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, dp, d, d, d, dp, ci, dp, dp]
-    lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, dp, ci]
+    lib.oracle_eddy.argtypes = [i64, dp, i64, ip, dp, d, d, d, dp, ci, ci, dp]
+    lib.oracle_rhs.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, ci, dp, ci]
+    lib.oracle_rhs_complex.argtypes = [i64, dp, i64, ip, dp, dp, dp, dp, d, d, d, dp, ci, ci, dp, dp]
+    lib.oracle_vjp.argtypes = [i64, dp, i64, ip, dp, dp, d, d, d, dp, ci, ci, dp, ci]
     lib.oracle_vjp_p.argtypes = [i64, dp, i64, ip, dp, dp, ci]
     for fn in ("oracle_geometry", "oracle_eddy", "oracle_rhs", "oracle_rhs_complex", "oracle_vjp", "oracle_vjp_p"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -86,20 +86,23 @@ def _check(status):
 
 
 EDDY_MODELS = {"smagorinsky": 0, "vreman": 1}
+CONVECTIVE_FORMS = {"advective": 0, "divergence": 1, "skew": 2, "rotational": 3, "emac": 4}
 
 
 class Params:
     """Physical parameters: density, molecular viscosity, model constant cs
     (0 = no eddy viscosity; Smagorinsky constant, Vreman uses c = 2.5 cs^2),
-    constant body-force acceleration and the eddy-viscosity model."""
+    constant body-force acceleration, the eddy-viscosity model and the form of
+    the convective term."""
 
-    def __init__(self, rho=1.0, mu=1e-3, cs=0.0, f=(0.1, -0.2, 0.3), model="smagorinsky"):
+    def __init__(self, rho=1.0, mu=1e-3, cs=0.0, f=(0.1, -0.2, 0.3), model="smagorinsky", form="advective"):
         self.rho, self.mu, self.cs = float(rho), float(mu), float(cs)
         self.f = np.asarray(f, dtype=np.float64).reshape(3).copy()
         self.model = EDDY_MODELS[model]
+        self.form = CONVECTIVE_FORMS[form]
 
     def args(self):
-        return (self.rho, self.mu, self.cs, _ptr(self.f), self.model)
+        return (self.rho, self.mu, self.cs, _ptr(self.f), self.model, self.form)
 
 
 def default_threads() -> int:

@@ -11,7 +11,8 @@ closed form
     int_e N_0^k0 N_1^k1 N_2^k2 N_3^k3 dx = 6 V k0! k1! k2! k3! / (k0+k1+k2+k3+3)!
 
 so the element contribution is
-    R^e_{a,i} = -rho sum_b (int N_a N_b) (G u_b)_i          convective
+    R^e_{a,i} = -rho sum_b (int N_a N_b) (K u_b)_i          convective, K = G
+                                                            (advective form)
                 - q_i int N_a + rho f_i int N_a             pressure, body
                 - mu (int 1) grad N_a . G_i,:               viscous
 with G = grad u and q = grad p constant on the element.  With mu_t = 0 the
@@ -56,12 +57,25 @@ def element_geometry(xe):
     return abs(D) / 6, grad
 
 
-def element_rhs(xe, ue, pe, rho, mu, f):
-    """Exact element vector R^e (4 x 3) for mu_t = 0."""
+# The convective forms as c = K u with K = G + alpha tr(G) I + beta G^T:
+# advective (u.grad)u; divergence div(u (x) u) = (u.grad)u + (div u)u;
+# skew-symmetric, their mean; rotational (curl u) x u = (u.grad)u - grad|u|^2/2;
+# EMAC 2 D(u) u + (div u) u.
+FORM_COEFFICIENTS = {"advective": (0, 0), "divergence": (1, 0), "skew": (Fraction(1, 2), 0),
+                     "rotational": (0, -1), "emac": (1, 1)}
+
+
+def element_rhs(xe, ue, pe, rho, mu, f, form="advective"):
+    """Exact element vector R^e (4 x 3) for mu_t = 0.  With G constant, the
+    convective integrand K u_h is linear in u_h, so int N_a K u_h =
+    sum_b (int N_a N_b) K u_b exactly."""
     vol, gN = element_geometry(xe)
     G = [[sum(ue[a][i] * gN[a][j] for a in range(4)) for j in range(3)] for i in range(3)]
     q = [sum(pe[a] * gN[a][j] for a in range(4)) for j in range(3)]
-    Gu = [[sum(G[i][j] * ue[b][j] for j in range(3)) for i in range(3)] for b in range(4)]
+    alpha, beta = FORM_COEFFICIENTS[form]
+    tr = G[0][0] + G[1][1] + G[2][2]
+    K = [[G[i][j] + (alpha * tr if i == j else 0) + beta * G[j][i] for j in range(3)] for i in range(3)]
+    Gu = [[sum(K[i][j] * ue[b][j] for j in range(3)) for i in range(3)] for b in range(4)]
     int1 = monomial_integral(vol, (0, 0, 0, 0))
     re = []
     for a in range(4):
@@ -82,22 +96,23 @@ def element_rhs(xe, ue, pe, rho, mu, f):
     return re
 
 
-def assemble_rhs(coords, conn, u, p, rho, mu, f, mu_elem=None):
+def assemble_rhs(coords, conn, u, p, rho, mu, f, mu_elem=None, form="advective"):
     """Exact assembled RHS as a list of Nn rows of 3 Fractions.  ``mu_elem``
-    optionally gives each element its own (rational) viscosity."""
+    optionally gives each element its own (rational) viscosity; ``form`` names
+    the convective form."""
     nn = len(coords)
     out = [[Fraction(0)] * 3 for _ in range(nn)]
     for e, tet in enumerate(conn):
         ids = [int(t) for t in tet]
         mu_e = mu if mu_elem is None else mu_elem[e]
-        re = element_rhs([coords[n] for n in ids], [u[n] for n in ids], [p[n] for n in ids], rho, mu_e, f)
+        re = element_rhs([coords[n] for n in ids], [u[n] for n in ids], [p[n] for n in ids], rho, mu_e, f, form)
         for a, n in enumerate(ids):
             for i in range(3):
                 out[n][i] += re[a][i]
     return out
 
 
-def assemble_vjp(coords, conn, u, lam, rho, mu, f):
+def assemble_vjp(coords, conn, u, lam, rho, mu, f, form="advective"):
     """Exact (dR/du)^T lam for mu_t = 0, by unit-step central differences of
     the quadratic element functional lam_e . R^e(u_e) (exact for quadratics)."""
     nn = len(coords)
@@ -109,7 +124,7 @@ def assemble_vjp(coords, conn, u, lam, rho, mu, f):
         le = [lam[n] for n in ids]
 
         def functional(ue):
-            re = element_rhs(xe, ue, zero_p, rho, mu, f)
+            re = element_rhs(xe, ue, zero_p, rho, mu, f, form)
             return sum(le[a][i] * re[a][i] for a in range(4) for i in range(3))
 
         base = [list(u[n]) for n in ids]
@@ -143,7 +158,7 @@ def assemble_vjp_p(coords, conn, u, lam, rho, mu, f):
     return out
 
 
-def assemble_jvp(coords, conn, u, p, du, dp, rho, mu, f):
+def assemble_jvp(coords, conn, u, p, du, dp, rho, mu, f, form="advective"):
     """Exact (dR/du) du + (dR/dp) dp for mu_t = 0: R is quadratic in u and
     affine in p, so the unit-step central difference is exact."""
     nn = len(coords)
@@ -151,6 +166,6 @@ def assemble_jvp(coords, conn, u, p, du, dp, rho, mu, f):
     minus = [[u[n][i] - du[n][i] for i in range(3)] for n in range(nn)]
     pp = [p[n] + dp[n] for n in range(nn)]
     pm = [p[n] - dp[n] for n in range(nn)]
-    rp = assemble_rhs(coords, conn, plus, pp, rho, mu, f)
-    rm = assemble_rhs(coords, conn, minus, pm, rho, mu, f)
+    rp = assemble_rhs(coords, conn, plus, pp, rho, mu, f, form=form)
+    rm = assemble_rhs(coords, conn, minus, pm, rho, mu, f, form=form)
     return [[(rp[n][i] - rm[n][i]) / 2 for i in range(3)] for n in range(nn)]

@@ -28,11 +28,16 @@
  *   R^e_a = sum_g (V/4) N_a(g) r^g - mu_e V G grad N_a,
  *   R_n = sum over (e, a) with node(e, a) = n of R^e_a.
  *
+ * The convective term may instead take the divergence, skew-symmetric,
+ * rotational or EMAC form (convective() in element_body.inc); the default is
+ * the advective form above.
+ *
  * Velocity vector-Jacobian product g = (dR/du)^T lambda (not in the paper; the
  * adjoint form of the same assembly), per element with lambda^g, Lambda =
- * grad lambda, Phi = Lambda : G:
+ * grad lambda, Phi = Lambda : G, for the advective form:
  *   g_b = -rho sum_g (V/4) [ N_b(g) G^T lambda^g + lambda^g (u^g . grad N_b) ]
  *         - mu_e V Lambda grad N_b - V Phi d mu_t / d u_b,
+ * (the other forms add their terms by the chain rule in element_vjp),
  *   d mu_t / d u_{b,k} = rho (cs Delta)^2 (2/|S|) sum_j S_kj d_j N_b  (0 if |S| = 0).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
@@ -50,6 +55,8 @@ typedef struct {
     double rho, mu, cs;
     double f[3];
     int model; /* eddy viscosity: 0 Smagorinsky, 1 Vreman; none when cs == 0 */
+    int form;  /* convective form: 0 advective, 1 divergence, 2 skew-symmetric,
+                  3 rotational, 4 EMAC (see convective() in element_body.inc) */
 } oracle_params;
 
 /* Symmetric 4-point rule on the tetrahedron, exact for degree 2. */
@@ -124,12 +131,26 @@ static int gather_element(int64_t nn, const double *x, const int32_t *conn, int6
     return 1;
 }
 
-static void set_params(oracle_params *prm, double rho, double mu, double cs, const double *f, int model) {
+static void set_params(oracle_params *prm, double rho, double mu, double cs, const double *f, int model,
+                       int form) {
     prm->rho = rho;
     prm->mu = mu;
     prm->cs = cs;
     for (int i = 0; i < 3; ++i) prm->f[i] = f[i];
     prm->model = model;
+    prm->form = form;
+}
+
+/* Each convective form of convective() written as
+ *   c = G u + alpha (tr G) u + beta G^T u,
+ * using div(u (x) u) = (u . grad) u + (div u) u and
+ * (curl u) x u = (u . grad) u - grad(|u|^2 / 2) = G u - G^T u.
+ * Used only by the VJP's chain rule; the forward evaluates the definitions. */
+static void form_coefficients(int form, double *alpha, double *beta) {
+    static const double tab[5][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.5, 0.0}, {0.0, -1.0}, {1.0, 1.0}};
+    const int k = (form >= 0 && form < 5) ? form : 0;
+    *alpha = tab[k][0];
+    *beta = tab[k][1];
 }
 
 /* D = d mu_t / d G (D_ij = d mu_t / d G_ij) at velocity gradient G, for the
@@ -216,9 +237,9 @@ int oracle_geometry(int64_t nn, const double *x, int64_t ne, const int32_t *conn
 
 /* Per-element eddy viscosity mu_t (ne values). */
 int oracle_eddy(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-                double rho, double mu, double cs, const double *f, int model, double *mu_t) {
+                double rho, double mu, double cs, const double *f, int model, int form, double *mu_t) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f, model);
+    set_params(&prm, rho, mu, cs, f, model, form);
     for (int64_t e = 0; e < ne; ++e) {
         int32_t ids[4];
         double xe[4][3], gN[4][3], V, D, ue[4][3], pe[4] = {0, 0, 0, 0}, G[3][3], S[3][3], q[3], sm;
@@ -236,10 +257,10 @@ int oracle_eddy(int64_t nn, const double *x, int64_t ne, const int32_t *conn, co
  * thread sums into a private copy of rhs, the copies are added at the end in
  * thread order (deterministic for a fixed thread count). */
 int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-               const double *p, double rho, double mu, double cs, const double *f, int model, double *rhs,
+               const double *p, double rho, double mu, double cs, const double *f, int model, int form, double *rhs,
                int nthreads) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f, model);
+    set_params(&prm, rho, mu, cs, f, model, form);
     const int nt = n_threads_or_default(nthreads);
     double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
     if (!part) return ORACLE_NOMEM;
@@ -289,10 +310,10 @@ int oracle_rhs(int64_t nn, const double *x, int64_t ne, const int32_t *conn, con
  * serial. */
 int oracle_rhs_complex(int64_t nn, const double *x, int64_t ne, const int32_t *conn,
                        const double *u_re, const double *u_im, const double *p_re, const double *p_im,
-                       double rho, double mu, double cs, const double *f, int model, double *r_re,
+                       double rho, double mu, double cs, const double *f, int model, int form, double *r_re,
                        double *r_im) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f, model);
+    set_params(&prm, rho, mu, cs, f, model, form);
     double complex *acc = (double complex *)calloc((size_t)nn * 3, sizeof(double complex));
     if (!acc) return ORACLE_NOMEM;
     for (int64_t e = 0; e < ne; ++e) {
@@ -342,6 +363,8 @@ static void element_vjp(const double gN[4][3], double V, const double ue[4][3],
     for (int b = 0; b < 4; ++b)
         for (int k = 0; k < 3; ++k) ge[b][k] = 0;
 
+    double alpha, beta;
+    form_coefficients(prm->form, &alpha, &beta);
     const double w = V / 4.0;
     for (int g = 0; g < 4; ++g) {
         double N[4], ug[3], lg[3];
@@ -354,13 +377,28 @@ static void element_vjp(const double gN[4][3], double V, const double ue[4][3],
                 lg[j] += N[a] * le[a][j];
             }
         }
+        /* lambda^g . c(u^g) with c = K u^g, K = G + alpha tr(G) I + beta G^T.
+         * d/du_{b,k} = N_b (K^T lambda^g)_k + sum_n d_n N_b d(lambda^g . c)/dG_kn,
+         * d(lambda^g . c)/dG_kn = lambda^g_k u^g_n + alpha delta_kn (lambda^g . u^g)
+         *                         + beta u^g_k lambda^g_n. */
+        const double trG = G[0][0] + G[1][1] + G[2][2];
+        double lu = 0;
+        for (int j = 0; j < 3; ++j) lu += lg[j] * ug[j];
         for (int b = 0; b < 4; ++b) {
-            double udn = 0;
-            for (int j = 0; j < 3; ++j) udn += ug[j] * gN[b][j];
+            double udn = 0, ldn = 0;
+            for (int j = 0; j < 3; ++j) {
+                udn += ug[j] * gN[b][j];
+                ldn += lg[j] * gN[b][j];
+            }
             for (int k = 0; k < 3; ++k) {
-                double gtl = 0;
-                for (int i = 0; i < 3; ++i) gtl += lg[i] * G[i][k];
-                ge[b][k] += -prm->rho * w * (N[b] * gtl + lg[k] * udn);
+                double gtl = 0, gl = 0;
+                for (int i = 0; i < 3; ++i) {
+                    gtl += lg[i] * G[i][k];
+                    gl += G[k][i] * lg[i];
+                }
+                const double ktl = gtl + alpha * trG * lg[k] + beta * gl;
+                const double dg = lg[k] * udn + alpha * lu * gN[b][k] + beta * ug[k] * ldn;
+                ge[b][k] += -prm->rho * w * (N[b] * ktl + dg);
             }
         }
     }
@@ -380,10 +418,10 @@ static void element_vjp(const double gN[4][3], double V, const double ue[4][3],
 /* Velocity vector-Jacobian product g = (dR/du)^T lam (nn x 3), FP64, OpenMP as
  * in oracle_rhs. */
 int oracle_vjp(int64_t nn, const double *x, int64_t ne, const int32_t *conn, const double *u,
-               const double *lam, double rho, double mu, double cs, const double *f, int model, double *grad,
+               const double *lam, double rho, double mu, double cs, const double *f, int model, int form, double *grad,
                int nthreads) {
     oracle_params prm;
-    set_params(&prm, rho, mu, cs, f, model);
+    set_params(&prm, rho, mu, cs, f, model, form);
     const int nt = n_threads_or_default(nthreads);
     double *part = (double *)calloc((size_t)nt * (size_t)nn * 3, sizeof(double));
     if (!part) return ORACLE_NOMEM;

@@ -1,0 +1,240 @@
+"""Pins of the oracle's convective forms (advective, divergence,
+skew-symmetric, rotational, EMAC) against facts that do not come from the
+oracle: the exact rational checker (which writes every form as
+c = G u + alpha tr(G) u + beta G^T u, while the oracle evaluates each form's
+definition), closed forms for linear fields, the kinetic-energy and momentum
+budgets each form has by the divergence theorem, rotation invariance and
+complex-step differentiation.  CPU only."""
+
+from fractions import Fraction
+from math import factorial
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_2403_08777_amd import synth
+from tests.test_oracle_pins import consistent_mass, dyadic_field, dyadic_mesh, frac_to_np
+
+F = np.array(synth.BODY_FORCE)
+FORMS = ["advective", "divergence", "skew", "rotational", "emac"]
+
+
+def conv_params(form, rho=1.3):
+    """Convective term only: no viscosity, pressure or body force."""
+    return oracle.Params(rho, 0.0, 0.0, (0.0, 0.0, 0.0), form=form)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_forms_exact_rational(oracle_lib, form):
+    coords, conn, xf = dyadic_mesh(2, 41)
+    rng = np.random.default_rng(42)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    pq, pf = dyadic_field(rng, len(coords), 1)
+    pq = [row[0] for row in pq]
+    rho, mu = Fraction(5, 4), Fraction(3, 1000)
+    fq = [Fraction(1, 10), Fraction(-2, 10), Fraction(3, 10)]
+    ref = frac_to_np(exact.assemble_rhs(coords, conn, uq, pq, rho, mu, fq, form=form))
+    got = oracle.rhs(xf, conn, uf, pf[:, 0], oracle.Params(float(rho), float(mu), 0.0, F, form=form))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+def _linear_field_convection(form, A, u):
+    """Closed form of the convective field for u(x) = A x + c at the nodal
+    values u (rows): grad u = A everywhere.  Rotational uses the identity
+    (curl u) x u = (A - A^T) u rather than a cross product."""
+    tr = np.trace(A)
+    if form == "advective":
+        return u @ A.T
+    if form == "divergence":
+        return u @ A.T + tr * u
+    if form == "skew":
+        return u @ A.T + 0.5 * tr * u
+    if form == "rotational":
+        return u @ (A - A.T).T
+    return u @ (A + A.T).T + tr * u  # EMAC
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_forms_linear_field_closed_form(oracle_lib, form):
+    """For a linear velocity the convective field is linear too, so its
+    Galerkin projection is the consistent mass matrix applied to its nodal
+    values: R = -rho M c(u_n).  A is non-symmetric with non-zero trace, so
+    every coefficient and every transposition is visible."""
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 3))
+    c = rng.standard_normal(3)
+    u = m.coords @ A.T + c
+    rho = 1.3
+    got = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), conv_params(form, rho))
+    ref = -rho * consistent_mass(m.coords, m.conn) @ _linear_field_convection(form, A, u)
+    assert oracle.rel_l2(got, ref) < 1e-13
+
+
+def boundary_faces(coords, conn):
+    """Faces that belong to one tetrahedron only, as (node ids, outward unit
+    normal, area)."""
+    count = {}
+    for e, tet in enumerate(conn):
+        for skip in range(4):
+            face = tuple(sorted(int(tet[k]) for k in range(4) if k != skip))
+            count.setdefault(face, []).append((e, int(tet[skip])))
+    out = []
+    for face, owners in count.items():
+        if len(owners) != 1:
+            continue
+        a, b, c = (coords[n] for n in face)
+        nrm = np.cross(b - a, c - a)
+        if np.dot(nrm, coords[owners[0][1]] - a) > 0:
+            nrm = -nrm
+        area = 0.5 * np.linalg.norm(nrm)
+        out.append((face, nrm / np.linalg.norm(nrm), area))
+    return out
+
+
+def tri_monomial(area, idx):
+    """Integral over a triangle of prod of barycentric coordinates lambda_i for
+    i in idx (repeats allowed): 2 A prod(e_k!) / (sum e_k + 2)!."""
+    e = [idx.count(k) for k in range(3)]
+    return 2.0 * area * np.prod([factorial(v) for v in e]) / factorial(sum(e) + 2)
+
+
+def flux_energy(coords, conn, u):
+    """oint (u . n) |u|^2 dS over the domain boundary, exactly for the P1 field."""
+    tot = 0.0
+    for face, n, area in boundary_faces(coords, conn):
+        uf = u[list(face)]
+        for i in range(3):
+            for j in range(3):
+                for k in range(3):
+                    tot += np.dot(uf[i], n) * np.dot(uf[j], uf[k]) * tri_monomial(area, [i, j, k])
+    return tot
+
+
+def flux_momentum(coords, conn, u):
+    """(oint u (u . n) dS, oint |u|^2 n dS) for the P1 field, exactly."""
+    conv = np.zeros(3)
+    pres = np.zeros(3)
+    for face, n, area in boundary_faces(coords, conn):
+        uf = u[list(face)]
+        for i in range(3):
+            for j in range(3):
+                w = tri_monomial(area, [i, j])
+                conv += uf[i] * np.dot(uf[j], n) * w
+                pres += np.dot(uf[i], uf[j]) * n * w
+    return conv, pres
+
+
+def test_boundary_quadrature_sanity():
+    """The boundary helpers on the unit cube: total area 6, oint n = 0, and
+    the flux of a constant field u through the boundary vanishes."""
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    faces = boundary_faces(m.coords, m.conn)
+    assert abs(sum(a for _, _, a in faces) - 6.0) < 1e-12
+    assert np.abs(sum(a * n for _, n, a in faces)).max() < 1e-12
+    u = np.tile([0.3, -0.7, 1.1], (m.n_nodes, 1))
+    assert abs(flux_energy(m.coords, m.conn, u)) < 1e-12
+    # x . n integrates to 3 |cell| = 3 (divergence of x)
+    assert abs(sum(a * np.dot(m.coords[list(f)].mean(0), n) for f, n, a in faces) - 3.0) < 1e-12
+
+
+@pytest.mark.parametrize("form,factor", [("skew", 0.5), ("emac", 1.0), ("rotational", 0.0)])
+def test_forms_kinetic_energy_budget(oracle_lib, form, factor):
+    """sum_n u_n . R_n = -rho int u . c(u) dx exactly (the 4-point rule is exact
+    for the degree-2 integrand).  For the skew-symmetric form u . c =
+    div(u |u|^2 / 2), for EMAC u . c = div(u |u|^2), for the rotational form
+    u . c = 0 pointwise, so the sum is -rho factor oint (u . n)|u|^2 dS: the
+    convective term exchanges no kinetic energy inside the domain."""
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    rng = np.random.default_rng(17)
+    u = rng.standard_normal((m.n_nodes, 3))
+    rho = 1.3
+    R = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), conv_params(form, rho))
+    got = float(np.sum(u * R))
+    ref = -rho * factor * flux_energy(m.coords, m.conn, u)
+    scale = float(np.sum(np.abs(u * R)))
+    assert abs(got - ref) <= 1e-13 * scale
+    # with u = 0 on the boundary the exchange is zero for all three forms
+    bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
+    u[bnd] = 0.0
+    R = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), conv_params(form, rho))
+    assert abs(float(np.sum(u * R))) <= 1e-13 * float(np.sum(np.abs(u * R)))
+    if form != "rotational":
+        # the advective form does exchange energy for a compressible P1 field
+        Ra = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), conv_params("advective", rho))
+        assert abs(float(np.sum(u * Ra))) > 1e-6 * float(np.sum(np.abs(u * Ra)))
+
+
+@pytest.mark.parametrize("form", ["divergence", "emac"])
+def test_forms_momentum_budget(oracle_lib, form):
+    """sum_n R_n = -rho int c(u) dx (partition of unity; c is linear on each
+    element).  Divergence form: c = div(u (x) u), so the sum is
+    -rho oint u (u . n); EMAC: c = div(u (x) u) + grad(|u|^2 / 2), so it is
+    -rho oint [u (u . n) + |u|^2 n / 2]."""
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    u = np.random.default_rng(18).standard_normal((m.n_nodes, 3))
+    rho = 1.3
+    R = oracle.rhs(m.coords, m.conn, u, np.zeros(m.n_nodes), conv_params(form, rho))
+    conv, pres = flux_momentum(m.coords, m.conn, u)
+    ref = -rho * (conv + (0.5 * pres if form == "emac" else 0.0))
+    assert np.abs(R.sum(0) - ref).max() <= 1e-13 * np.abs(R).sum()
+
+
+@pytest.mark.parametrize("form", FORMS[1:])
+def test_forms_constant_field_and_rotation_invariance(oracle_lib, form):
+    m = synth.cube_mesh(4, jitter=True, permute=True)
+    uc = np.tile([0.3, -1.2, 2.5], (m.n_nodes, 1))
+    assert np.abs(oracle.rhs(m.coords, m.conn, uc, np.zeros(m.n_nodes), conv_params(form))).max() < 1e-13
+    u, p = synth.taylor_green(m)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F, form=form)
+    r = oracle.rhs(m.coords, m.conn, u, p, prm)
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    t = rng.standard_normal(3)
+    r2 = oracle.rhs(m.coords @ Q.T + t, m.conn, u @ Q.T, p, oracle.Params(1.0, 1e-3, 0.1, Q @ F, form=form))
+    assert oracle.rel_l2(r2, r @ Q.T) < 1e-13
+
+
+@pytest.mark.parametrize("form", FORMS[1:])
+def test_forms_vjp_exact_rational(oracle_lib, form):
+    coords, conn, xf = dyadic_mesh(2, 43)
+    rng = np.random.default_rng(44)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    lq, lf = dyadic_field(rng, len(coords), 3)
+    rho, mu = Fraction(3, 2), Fraction(1, 64)
+    ref = frac_to_np(exact.assemble_vjp(coords, conn, uq, lq, rho, mu, [Fraction(0)] * 3, form=form))
+    got = oracle.vjp(xf, conn, uf, lf, oracle.Params(float(rho), float(mu), 0.0, F, form=form))
+    assert oracle.rel_l2(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("form,model", [("divergence", "smagorinsky"), ("skew", "vreman"),
+                                        ("rotational", "smagorinsky"), ("emac", "vreman")])
+def test_forms_vjp_complex_step_dense_jacobian(oracle_lib, form, model):
+    """With the eddy viscosity on, the VJP's convective chain rule and the
+    model derivative together against the complex-step Jacobian of the
+    definition-based forward."""
+    m = synth.cube_mesh(2, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    prm = oracle.Params(1.0, 1e-3, 0.1, F, model=model, form=form)
+    jac = oracle.dense_jacobian_complex_step(m.coords, m.conn, u, p, prm)
+    g_ref = (jac.T @ lam.reshape(-1)).reshape(-1, 3)
+    assert oracle.rel_l2(oracle.vjp(m.coords, m.conn, u, lam, prm), g_ref) < 1e-12
+
+
+@pytest.mark.parametrize("form", ["skew", "emac"])
+def test_forms_jvp_exact_rational(oracle_lib, form):
+    coords, conn, xf = dyadic_mesh(2, 45)
+    rng = np.random.default_rng(46)
+    uq, uf = dyadic_field(rng, len(coords), 3)
+    dq, df = dyadic_field(rng, len(coords), 3)
+    pq, pf = dyadic_field(rng, len(coords), 1)
+    eq, ef = dyadic_field(rng, len(coords), 1)
+    pq, eq = [r[0] for r in pq], [r[0] for r in eq]
+    rho, mu = Fraction(1), Fraction(1, 32)
+    fq = [Fraction(0)] * 3
+    ref = frac_to_np(exact.assemble_jvp(coords, conn, uq, pq, dq, eq, rho, mu, fq, form=form))
+    got = oracle.jvp(xf, conn, uf, pf[:, 0], df, ef[:, 0], oracle.Params(1.0, float(mu), 0.0, F, form=form))
+    assert oracle.rel_l2(got, ref) < 1e-14
