@@ -211,3 +211,31 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b, dtype=np.float64).reshape(-1)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def lumped_volume(coords, conn):
+    """Row-sum lumped volume V^L_n = sum over elements e containing n of
+    V_e / 4 (the P1 lumped mass divided by the density), shape (Nn,)."""
+    vol, _ = geometry(coords, conn)
+    c = _i32(conn)
+    out = np.zeros(np.asarray(coords).shape[0])
+    np.add.at(out, c.reshape(-1), np.repeat(vol / 4.0, 4))
+    return out
+
+
+def explicit_update(coords, conn, u, p, prm: Params, dt, mask=None):
+    """One explicit momentum stage of the fractional-step scheme (Sec. II:
+    explicit time integration of the momentum equation): with the lumped
+    mass M_L,n = rho V^L_n,
+        u_new[n, i] = u[n, i] + dt R[n, i] / (rho V^L_n)
+    for free components, and u_new[n, i] = u[n, i] where bit i of mask[n] is
+    set (Dirichlet-constrained components keep the value the caller put in
+    u).  Returns (u_new, R)."""
+    u = _f64(u)
+    R = rhs(coords, conn, u, p, prm)
+    step = u + dt * R / (prm.rho * lumped_volume(coords, conn))[:, None]
+    if mask is None:
+        return step, R
+    m = np.asarray(mask, dtype=np.uint8)
+    fixed = np.stack([(m >> i) & 1 for i in range(3)], axis=1).astype(bool)
+    return np.where(fixed, u, step), R
