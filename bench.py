@@ -172,6 +172,8 @@ def main():
     # launch stream; with atomic scatter, ACCUMULATE skips the zero-fill
     # kernel (the gather scatter has none)
     def kernel_ms(fn, reps):
+        for _ in range(2):  # first launches of a kernel load its code object
+            fn()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
             a.record()
@@ -230,6 +232,42 @@ def main():
         forms["mixed_fwd_vjp_elems_per_s"] = ne / (ms32 * 1e-3)
         forms["mixed_fwd_elems_per_s"] = ne / (f32[0] * 1e-3)
 
+    # the selectable physics (eddy-viscosity models, convective forms) and the
+    # other derivative products, FP64 on the same mesh: per-call kernel times
+    # and the resulting rate of one forward + VJP pair
+    variants = {}
+    pr_g = torch.empty(nn, dtype=torch.float64, device=dev)
+    du = torch.randn_like(u)
+    dpr = torch.randn_like(p)
+    for tag, cs, model, conv in (("smagorinsky", 0.1, "smagorinsky", "advective"),
+                                 ("vreman", 0.1, "vreman", "advective"),
+                                 ("divergence", wl.cs, "smagorinsky", "divergence"),
+                                 ("skew", wl.cs, "smagorinsky", "skew"),
+                                 ("rotational", wl.cs, "smagorinsky", "rotational"),
+                                 ("emac", wl.cs, "smagorinsky", "emac")):
+        vp = api.Params(wl.rho, wl.mu, cs, wl.body_force, model, conv)
+        tf = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, vp, out=scratch, accumulate=acc), args.kernel_reps)[0]
+        tv = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, vp, out=scratch, accumulate=acc),
+                       args.kernel_reps)[0]
+        variants[tag] = {"eddy_model": model, "smagorinsky_cs": cs, "convective_form": conv, "fwd_ms": tf,
+                         "vjp_ms": tv, "fwd_vjp_elems_per_s": ne / ((tf + tv) * 1e-3)}
+    tj = kernel_ms(lambda: api.assemble_rhs_jvp(mesh, u, du, dpr, prm, out=scratch, accumulate=acc),
+                   args.kernel_reps)[0]
+    tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[0]
+    variants["jvp"] = {"ms": tj, "elems_per_s": ne / (tj * 1e-3)}
+    variants["vjp_p"] = {"ms": tp, "elems_per_s": ne / (tp * 1e-3)}
+    # explicit momentum stage u + dt R / (rho V^L) with a boundary Dirichlet
+    # mask; with the gather scatter the update is fused into the gather kernel
+    bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
+    mask = mesh.to_mesh_order(to_dev(np.where(bnd, 7.0, 0.0), torch.float64)).to(torch.uint8)
+    tu = kernel_ms(lambda: api.explicit_update(mesh, u, p, prm, 1e-3, mask, out=scratch), args.kernel_reps)[0]
+    variants["explicit_update"] = {"ms": tu, "elems_per_s": ne / (tu * 1e-3),
+                                   "fused": mesh.info["scatter"] == "patch_gather",
+                                   "vs_forward_ms": tu - kernels["fwd"]["mean_ms"]}
+    log("[bench] variants (fwd+vjp G elem/s): " + ", ".join(
+        f"{k} {v['fwd_vjp_elems_per_s'] / 1e9:.2f}" for k, v in variants.items() if "fwd_vjp_elems_per_s" in v)
+        + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us")
+
     result = {
         "metric": "elements/s (FP64 forward + velocity VJP assembly)",
         "value": value,
@@ -254,6 +292,7 @@ def main():
                      "flops_per_element": FLOPS_PER_ELEMENT[(dom, eddy)], "elements_per_launch": ne},
         "kernels": kernels,
         "forms": forms,
+        "variants": variants,
         "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms},
     }
 

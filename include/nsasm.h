@@ -98,6 +98,26 @@ typedef enum {
 #define NSASM_EDDY_SMAGORINSKY 0u
 #define NSASM_EDDY_VREMAN 1u
 
+/* Convective forms (nsasm_params.convective_form).  The paper calls Alya's
+ * convection scheme energy preserving (Sec. II) without printing its discrete
+ * form; these are the standard Galerkin forms of the same continuous term
+ * rho (u . grad) u, replacing rho G u_h in the integrand of R^e_a:
+ *   ADVECTIVE   (u . grad) u                          = G u
+ *   DIVERGENCE  div(u (x) u)                          = G u + tr(G) u
+ *   SKEW        the mean of the two above             = G u + tr(G) u / 2
+ *   ROTATIONAL  (curl u) x u                          = G u - G^T u
+ *   EMAC        2 D(u) u + (div u) u, D = (G + G^T)/2 = G u + G^T u + tr(G) u
+ * (EMAC: Charnyi, Heister, Olshanskii, Rebholz, J. Comput. Phys. 2017).  With
+ * the 4-point rule these integrate exactly, so summed over the mesh the
+ * skew-symmetric, rotational and EMAC forms exchange no kinetic energy
+ * (sum_n u_n . R^conv_n) except through the boundary flux of u |u|^2 (zero
+ * for ROTATIONAL, and for the others when u = 0 on the boundary). */
+#define NSASM_CONVECTIVE_ADVECTIVE 0u
+#define NSASM_CONVECTIVE_DIVERGENCE 1u
+#define NSASM_CONVECTIVE_SKEW 2u
+#define NSASM_CONVECTIVE_ROTATIONAL 3u
+#define NSASM_CONVECTIVE_EMAC 4u
+
 typedef struct {
     double rho;            /* density, constant (> 0) */
     double mu;             /* molecular dynamic viscosity, constant (>= 0) */
@@ -105,6 +125,8 @@ typedef struct {
     double body_force[3];  /* constant body-force acceleration f; term is +rho f */
     uint32_t flags;        /* bitwise OR of NSASM_ACCUMULATE, or 0 */
     uint32_t eddy_model;   /* NSASM_EDDY_SMAGORINSKY (0) or NSASM_EDDY_VREMAN */
+    uint32_t convective_form; /* NSASM_CONVECTIVE_* (0 = advective) */
+    uint32_t reserved;     /* must be 0 */
 } nsasm_params;
 
 typedef struct {
@@ -231,6 +253,38 @@ nsasm_status nsasm_assemble_rhs_vjp_p(const nsasm_mesh *mesh, const nsasm_params
 nsasm_status nsasm_assemble_rhs_jvp(const nsasm_mesh *mesh, const nsasm_params *params,
                                     nsasm_precision precision, const void *u, const void *du,
                                     const void *dp, void *drhs, void *stream);
+
+/*
+ * Lumped volume of every node, V^L_n = sum over the elements e containing n
+ * of V_e / 4: the row sums of the P1 mass matrix divided by the density,
+ * computed once at mesh creation.  lumped: device, n_nodes doubles, mesh
+ * order.  Asynchronous on stream.
+ */
+nsasm_status nsasm_mesh_lumped_volume(const nsasm_mesh *mesh, double *lumped, void *stream);
+
+/*
+ * One explicit momentum stage of the fractional-step scheme (Sec. II: the
+ * momentum equation is integrated explicitly; the RHS assembled here is what
+ * the stage advances).  With the lumped mass M_L,n = rho V^L_n:
+ *   rhs   = the assembled RHS of (u, p)       (as nsasm_assemble_rhs)
+ *   u_new[n][i] = u[n][i] + dt rhs[n][i] / (rho V^L_n)   if bit i of mask[n] is 0,
+ *   u_new[n][i] = u[n][i]                               if it is 1
+ * (Dirichlet components keep the value the caller stored in u).
+ * u              : device, n_nodes x 3, mesh order.   p : device, n_nodes.
+ * dirichlet_mask : device, n_nodes bytes (bits 0..2 = x, y, z), or NULL (none).
+ * rhs            : device, n_nodes x 3, receives the assembled RHS; may be NULL
+ *                  when the mesh uses NSASM_SCATTER_PATCH_GATHER (the update is
+ *                  then fused into the gather kernel and the RHS never reaches
+ *                  memory), required otherwise.
+ * u_new          : device, n_nodes x 3; may be u itself (in-place update) but
+ *                  must not otherwise overlap an input.
+ * dt: finite.  params->flags must be 0.  Asynchronous on stream.
+ * Errors: as nsasm_assemble_rhs, plus INVALID_ARGUMENT for a non-finite dt,
+ * non-zero flags, a missing rhs or overlapping buffers.
+ */
+nsasm_status nsasm_explicit_update(const nsasm_mesh *mesh, const nsasm_params *params,
+                                   nsasm_precision precision, double dt, const void *u, const void *p,
+                                   const uint8_t *dirichlet_mask, void *rhs, void *u_new, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nsasm_last_error(void);

@@ -35,7 +35,8 @@ class NsasmError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_double), ("mu", ctypes.c_double), ("smagorinsky_cs", ctypes.c_double),
-                ("body_force", ctypes.c_double * 3), ("flags", ctypes.c_uint32), ("eddy_model", ctypes.c_uint32)]
+                ("body_force", ctypes.c_double * 3), ("flags", ctypes.c_uint32), ("eddy_model", ctypes.c_uint32),
+                ("convective_form", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _MeshOptions(ctypes.Structure):
@@ -66,10 +67,13 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_assemble_rhs_vjp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
     lib.nsasm_assemble_rhs_vjp_p.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp]
     lib.nsasm_assemble_rhs_jvp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp, vp]
+    lib.nsasm_mesh_lumped_volume.argtypes = [vp, vp, vp]
+    lib.nsasm_explicit_update.argtypes = [vp, ctypes.POINTER(_Params), st, ctypes.c_double, vp, vp, vp, vp, vp,
+                                          vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
                  "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp", "nsasm_assemble_rhs_vjp_p",
-                 "nsasm_assemble_rhs_jvp"):
+                 "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -106,24 +110,29 @@ def _dev(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
 
 
 EDDY_MODELS = {"smagorinsky": 0, "vreman": 1}
+CONVECTIVE_FORMS = {"advective": 0, "divergence": 1, "skew": 2, "rotational": 3, "emac": 4}
 
 
 @dataclass
 class Params:
     """Density, molecular viscosity, eddy-viscosity model constant C_s
-    (0 = no eddy viscosity), constant body-force acceleration and the model
-    ("smagorinsky", or "vreman" with c = 2.5 C_s^2)."""
+    (0 = no eddy viscosity), constant body-force acceleration, the model
+    ("smagorinsky", or "vreman" with c = 2.5 C_s^2) and the convective form
+    ("advective", "divergence", "skew", "rotational" or "emac"; see
+    NSASM_CONVECTIVE_* in nsasm.h)."""
 
     rho: float = 1.0
     mu: float = 1e-3
     cs: float = 0.0
     body_force: tuple = (0.1, -0.2, 0.3)
     eddy_model: str = "smagorinsky"
+    convective_form: str = "advective"
 
     def c_struct(self, accumulate: bool = False) -> _Params:
         f = tuple(float(v) for v in self.body_force)
         return _Params(float(self.rho), float(self.mu), float(self.cs), (ctypes.c_double * 3)(*f),
-                       ACCUMULATE if accumulate else 0, EDDY_MODELS[self.eddy_model])
+                       ACCUMULATE if accumulate else 0, EDDY_MODELS[self.eddy_model],
+                       CONVECTIVE_FORMS[self.convective_form], 0)
 
 
 class Mesh:
@@ -191,6 +200,13 @@ class Mesh:
         out = torch.empty_like(t)
         fn = lib.nsasm_to_mesh_order if to_mesh else lib.nsasm_from_mesh_order
         _check(fn(self.handle, ncomp, prec, t.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def lumped_volume(self, stream=None) -> torch.Tensor:
+        """float64 (Nn,), mesh order: V^L_n = sum of V_e / 4 over the elements
+        containing node n (the lumped mass divided by the density)."""
+        out = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device)
+        _check(lib.nsasm_mesh_lumped_volume(self.handle, out.data_ptr(), _stream(stream)))
         return out
 
     def to_mesh_order(self, t: torch.Tensor, stream=None) -> torch.Tensor:
@@ -275,6 +291,36 @@ def assemble_rhs_jvp(mesh: Mesh, u: torch.Tensor, du: torch.Tensor, dp: torch.Te
     prm = params.c_struct(accumulate)
     _check(lib.nsasm_assemble_rhs_jvp(mesh.handle, ctypes.byref(prm), prec, u.data_ptr(), du.data_ptr(),
                                       None if dp is None else dp.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def explicit_update(mesh: Mesh, u: torch.Tensor, p: torch.Tensor, params: Params, dt: float,
+                    dirichlet_mask: torch.Tensor = None, rhs: torch.Tensor = None, out: torch.Tensor = None,
+                    stream=None) -> torch.Tensor:
+    """One explicit momentum stage in mesh order: u + dt rhs / (rho V^L) for
+    free components, u for components whose bit (0..2) is set in the uint8
+    dirichlet_mask (Nn,).  ``rhs`` (Nn, 3) optionally receives the assembled
+    RHS; meshes that do not use the gather scatter need it as workspace, and
+    it is allocated here when not given.  ``out`` may be ``u`` itself (in-place
+    update).  Returns the updated velocity."""
+    prec = _precision_of(u)
+    nn = mesh.n_nodes
+    _dev(u, u.dtype, (nn, 3), "u")
+    _dev(p, u.dtype, (nn,), "p")
+    if dirichlet_mask is not None:
+        _dev(dirichlet_mask, torch.uint8, (nn,), "dirichlet_mask")
+    if rhs is None and mesh.info["scatter"] != "patch_gather":
+        rhs = torch.empty((nn, 3), dtype=u.dtype, device=u.device)
+    if rhs is not None:
+        _dev(rhs, u.dtype, (nn, 3), "rhs")
+    if out is None:
+        out = torch.empty((nn, 3), dtype=u.dtype, device=u.device)
+    else:
+        _dev(out, u.dtype, (nn, 3), "out")
+    prm = params.c_struct()
+    _check(lib.nsasm_explicit_update(mesh.handle, ctypes.byref(prm), prec, float(dt), u.data_ptr(), p.data_ptr(),
+                                     None if dirichlet_mask is None else dirichlet_mask.data_ptr(),
+                                     None if rhs is None else rhs.data_ptr(), out.data_ptr(), _stream(stream)))
     return out
 
 

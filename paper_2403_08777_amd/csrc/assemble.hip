@@ -52,14 +52,15 @@ constexpr int kThreads = 256;
 //   kVjp:     A = u, B = adjoint      -> (d rhs / d u)^T adjoint (3)
 //   kVjpP:    B = adjoint             -> (d rhs / d p)^T adjoint (1)
 //   kJvp:     A = u, B = du, C = dp   -> (d rhs / d u) du + (d rhs / d p) dp (3)
-enum Mode { kForward = 0, kVjp = 1, kVjpP = 2, kJvp = 3 };
+//   kMass:    no fields               -> lumped volume V^L (1), once per mesh
+enum Mode { kForward = 0, kVjp = 1, kVjpP = 2, kJvp = 3, kMass = 4 };
 
 template <int MODE>
 struct Fields {
-    static constexpr int NA = (MODE == kVjpP) ? 0 : 3;
-    static constexpr int NB = (MODE == kForward) ? 0 : 3;
+    static constexpr int NA = (MODE == kVjpP || MODE == kMass) ? 0 : 3;
+    static constexpr int NB = (MODE == kForward || MODE == kMass) ? 0 : 3;
     static constexpr int NC = (MODE == kForward || MODE == kJvp) ? 1 : 0;
-    static constexpr int NOUT = (MODE == kVjpP) ? 1 : 3;
+    static constexpr int NOUT = (MODE == kVjpP || MODE == kMass) ? 1 : 3;
 };
 
 template <typename T>
@@ -68,7 +69,13 @@ struct KParams {
     T mu;
     T rho_c;       // rho * model constant: cs^2 (Smagorinsky) or 2.5 cs^2 (Vreman)
     T rho_f[3];    // rho * f
+    T conv_a;      // convective form c = G u + conv_a tr(G) u + conv_b G^T u
+    T conv_b;
 };
+
+// Convective form: kAdvective is c = G u; kGeneral adds conv_a tr(G) u +
+// conv_b G^T u (divergence, skew-symmetric, rotational and EMAC forms).
+enum ConvForm { kAdvective = 0, kGeneral = 1 };
 
 // ------------------------------------------------------------ atomics
 
@@ -188,7 +195,7 @@ __device__ inline T eddy_viscosity(const T (&G)[3][3], T vol, T rho_c, T (&D)[3]
     return c * s;
 }
 
-template <typename T, int EDDY>
+template <typename T, int EDDY, int CONV>
 __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&pe)[4],
                                    const KParams<T> &P, T (&re)[4][3]) {
     T G[3][3];
@@ -210,17 +217,25 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
         U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
         b[i] = w4 * (P.rho_f[i] - q[i]);
     }
+    const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        T y[3];
+        T z[3], y[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) y[j] = sc * (ue[a][j] + U[j]) + sv * gN[a][j];
+        for (int j = 0; j < 3; ++j) {
+            z[j] = sc * (ue[a][j] + U[j]);
+            y[j] = z[j] + sv * gN[a][j];
+        }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) re[a][i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
+        for (int i = 0; i < 3; ++i) {
+            re[a][i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
+            if (CONV == kGeneral)
+                re[a][i] -= at * z[i] + P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
+        }
     }
 }
 
-template <typename T, int EDDY>
+template <typename T, int EDDY, int CONV>
 __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
                                    const KParams<T> &P, T (&ge)[4][3]) {
     T G[3][3], Lam[3][3];
@@ -245,22 +260,52 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
             for (int j = 0; j < 3; ++j) phi += Lam[i][j] * G[i][j];
         se = vol * phi;
     }
+    // W = (rho V / 20)(P + L (x) U) is the convective part of M; a general
+    // form K = G + conv_a tr(G) I + conv_b G^T turns K : W into
+    // G : (W + conv_a tr(W) I + conv_b W^T).
     T M[3][3];
+    if (CONV == kGeneral) {
+        T W[3][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
-            M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
-            if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
-        }
+            for (int j = 0; j < 3; ++j) {
+                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
+                W[k][j] = sc * (pkj + L[k] * U[j]);
+            }
+        const T atw = P.conv_a * (W[0][0] + W[1][1] + W[2][2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                M[k][j] = W[k][j] + P.conv_b * W[j][k] + sv * Lam[k][j];
+                if (k == j) M[k][j] += atw;
+                if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
+            }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
+                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
+                if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
+            }
+    }
+    const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const T w0 = le[b][0] + L[0], w1 = le[b][1] + L[1], w2 = le[b][2] + L[2];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            ge[b][k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) -
-                       sc * (G[0][k] * w0 + G[1][k] * w1 + G[2][k] * w2);
+        for (int k = 0; k < 3; ++k) {
+            // (K^T w)_k = (G^T w)_k + conv_a tr(G) w_k + conv_b (G w)_k
+            T kw = G[0][k] * w0 + G[1][k] * w1 + G[2][k] * w2;
+            if (CONV == kGeneral) {
+                const T wk = (k == 0) ? w0 : (k == 1) ? w1 : w2;
+                kw += at * wk + P.conv_b * (G[k][0] * w0 + G[k][1] * w1 + G[k][2] * w2);
+            }
+            ge[b][k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw;
+        }
     }
 }
 
@@ -281,7 +326,7 @@ __device__ inline void element_vjp_p(const T (&gN)[4][3], T vol, const T (&le)[4
 //   dR^e_a = -(V/4) dq - dG y_a - G dy_a,
 //   dy_a = (rho V / 20)(du_a + dU) + V (D : dG) grad N_a,
 // with dG = grad du, dq = grad dp and D = d mu_t / d G.
-template <typename T, int EDDY>
+template <typename T, int EDDY, int CONV>
 __device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&due)[4][3],
                                    const T (&dpe)[4], const KParams<T> &P, T (&dr)[4][3]) {
     T G[3][3], dG[3][3], dq[3];
@@ -309,29 +354,45 @@ __device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][
         U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
         dU[i] = due[0][i] + due[1][i] + due[2][i] + due[3][i];
     }
+    // general form: the extra term E z_a, E = conv_a tr(G) I + conv_b G^T,
+    // z_a = (rho V / 20)(u_a + U), differentiates to dE z_a + E dz_a
+    const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
+    const T dat = (CONV == kGeneral) ? P.conv_a * (dG[0][0] + dG[1][1] + dG[2][2]) : T(0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        T y[3], dy[3];
+        T z[3], dz[3], y[3], dy[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            y[j] = sc * (ue[a][j] + U[j]) + sv * gN[a][j];
-            dy[j] = sc * (due[a][j] + dU[j]) + dsv * gN[a][j];
+            z[j] = sc * (ue[a][j] + U[j]);
+            dz[j] = sc * (due[a][j] + dU[j]);
+            y[j] = z[j] + sv * gN[a][j];
+            dy[j] = dz[j] + dsv * gN[a][j];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i) {
             dr[a][i] = -w4 * dq[i] - (dG[i][0] * y[0] + dG[i][1] * y[1] + dG[i][2] * y[2]) -
                        (G[i][0] * dy[0] + G[i][1] * dy[1] + G[i][2] * dy[2]);
+            if (CONV == kGeneral)
+                dr[a][i] -= dat * z[i] + at * dz[i] +
+                            P.conv_b * (dG[0][i] * z[0] + dG[1][i] * z[1] + dG[2][i] * z[2] +
+                                        G[0][i] * dz[0] + G[1][i] * dz[1] + G[2][i] * dz[2]);
+        }
     }
 }
 
 // The element operation of a launch mode on gathered vertex data.
-template <typename T, int EDDY, int MODE>
+template <typename T, int EDDY, int CONV, int MODE>
 __device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3], const T (&eb)[4][3],
                                   const T (&ec)[4], const KParams<T> &P, T (&r)[4][3]) {
-    if (MODE == kForward) element_rhs<T, EDDY>(gN, vol, ea, ec, P, r);
-    if (MODE == kVjp) element_vjp<T, EDDY>(gN, vol, ea, eb, P, r);
+    if (MODE == kForward) element_rhs<T, EDDY, CONV>(gN, vol, ea, ec, P, r);
+    if (MODE == kVjp) element_vjp<T, EDDY, CONV>(gN, vol, ea, eb, P, r);
     if (MODE == kVjpP) element_vjp_p(gN, vol, eb, r);
-    if (MODE == kJvp) element_jvp<T, EDDY>(gN, vol, ea, eb, ec, P, r);
+    if (MODE == kJvp) element_jvp<T, EDDY, CONV>(gN, vol, ea, eb, ec, P, r);
+    if (MODE == kMass) {
+        // row-sum lumping of the P1 mass matrix: sum_b int N_a N_b = V/4
+#pragma unroll
+        for (int a = 0; a < 4; ++a) r[a][0] = vol * T(0.25);
+    }
 }
 
 template <typename T>
@@ -361,7 +422,7 @@ struct NodeFields {
 };
 
 // One thread per element, NOUT global atomic adds per vertex.
-template <typename T, int EDDY, int MODE>
+template <typename T, int EDDY, int CONV, int MODE>
 __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const int4 *__restrict__ conn,
                                                                const double *__restrict__ x, NodeFields<T> F,
                                                                KParams<T> P, T *__restrict__ out) {
@@ -388,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
     T gN[4][3], vol;
     to_field(g64, vol64, gN, vol);
     T r[4][3];
-    element_op<T, EDDY, MODE>(gN, vol, ea, eb, ec, P, r);
+    element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, r);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -402,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
 // sums in a fixed order.  GATHER = false adds each node sum to `out` with a
 // global atomic; GATHER = true stores it to the node-major partial-sum buffer
 // (position ref_slot of the patch reference), for k_gather_partials.
-template <typename T, int EDDY, int MODE, bool GATHER>
+template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, const int32_t *__restrict__ patch_off,
     const int32_t *__restrict__ patch_nodes, const int32_t *__restrict__ patch_node_start,
@@ -468,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
         tet_geometry(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
-        element_op<T, EDDY, MODE>(gN, vol, ea, eb, ec, P, r);
+        element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, r);
     }
     __syncthreads();  // node data is dead from here on; its bytes become slots
     if (t < nel) {
@@ -514,6 +575,54 @@ __global__ __launch_bounds__(kThreads) void k_gather_partials(int64_t nn, const 
     for (int i = 0; i < NOUT; ++i) out[NOUT * n + i] = accumulate ? out[NOUT * n + i] + acc[i] : acc[i];
 }
 
+// Explicit momentum stage fused into the gather: rhs_n is summed from the
+// patch partials as in k_gather_partials, optionally stored, and
+//   u_new[n, i] = u[n, i] + dt rhs[n, i] / (rho V^L_n)
+// for components whose bit i of mask[n] is clear (u_new[n, i] = u[n, i]
+// otherwise).  u_new may be u itself: each thread reads and writes only its
+// own node.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_update(int64_t nn, const int32_t *__restrict__ ref_off,
+                                                            const T *__restrict__ partial,
+                                                            const double *__restrict__ lumped, double rho,
+                                                            double dt, const T *u, const uint8_t *__restrict__ mask,
+                                                            T *__restrict__ rhs, T *u_new) {
+    const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (n >= nn) return;
+    T acc[3] = {T(0), T(0), T(0)};
+    const int64_t kb = ref_off[n], ke = ref_off[n + 1];
+    for (int64_t k = kb; k < ke; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc[i] += partial[3 * k + i];
+    if (rhs) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rhs[3 * n + i] = acc[i];
+    }
+    const T w = static_cast<T>(dt / (rho * lumped[n]));
+    const unsigned fixed = mask ? mask[n] : 0u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T ui = u[3 * n + i];
+        u_new[3 * n + i] = ((fixed >> i) & 1u) ? ui : ui + w * acc[i];
+    }
+}
+
+// The same update from an assembled rhs (atomic and patch scatters).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update(int64_t nn, const T *__restrict__ rhs,
+                                                     const double *__restrict__ lumped, double rho, double dt,
+                                                     const T *u, const uint8_t *__restrict__ mask, T *u_new) {
+    const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+    if (n >= nn) return;
+    const T w = static_cast<T>(dt / (rho * lumped[n]));
+    const unsigned fixed = mask ? mask[n] : 0u;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T ui = u[3 * n + i];
+        u_new[3 * n + i] = ((fixed >> i) & 1u) ? ui : ui + w * rhs[3 * n + i];
+    }
+}
+
 // ---------------------------------------------------------- host side
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
@@ -533,6 +642,9 @@ nsasm_status check_params(const nsasm_params *p) {
     if (p->flags & ~NSASM_ACCUMULATE) return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", p->flags);
     if (p->eddy_model != NSASM_EDDY_SMAGORINSKY && p->eddy_model != NSASM_EDDY_VREMAN)
         return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown eddy_model %u", p->eddy_model);
+    if (p->convective_form > NSASM_CONVECTIVE_EMAC)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown convective_form %u", p->convective_form);
+    if (p->reserved != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "reserved must be 0");
     return NSASM_OK;
 }
 
@@ -544,59 +656,121 @@ KParams<T> kernel_params(const nsasm_params &p) {
     const double c = (p.eddy_model == NSASM_EDDY_VREMAN ? 2.5 : 1.0) * p.smagorinsky_cs * p.smagorinsky_cs;
     k.rho_c = static_cast<T>(p.rho * c);
     for (int i = 0; i < 3; ++i) k.rho_f[i] = static_cast<T>(p.rho * p.body_force[i]);
+    // c = G u + a tr(G) u + b G^T u, from div(u (x) u) = G u + tr(G) u and
+    // (curl u) x u = G u - G^T u
+    static const double kForm[5][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.5, 0.0}, {0.0, -1.0}, {1.0, 1.0}};
+    k.conv_a = static_cast<T>(kForm[p.convective_form][0]);
+    k.conv_b = static_cast<T>(kForm[p.convective_form][1]);
     return k;
 }
 
-template <typename T, int EDDY, int MODE>
+// Explicit-update epilogue of a forward launch (see k_gather_update).
+template <typename T>
+struct Update {
+    double rho, dt;
+    const T *u;
+    const uint8_t *mask;
+    T *rhs;  // may be null
+    T *u_new;
+};
+
+// With the gather scatter and `up` set, the gather kernel applies the
+// explicit update instead of writing `out`.
+template <typename T, int EDDY, int CONV, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, T *out, bool accumulate,
-                    hipStream_t s) {
+                    const Update<T> *up, hipStream_t s) {
     constexpr int NOUT = Fields<MODE>::NOUT;
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
         T *partial = reinterpret_cast<T *>(m->partial);
-        k_assemble_patch<T, EDDY, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
+        k_assemble_patch<T, EDDY, CONV, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
             m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
             m->ref_slot, m->elem_pos, m->x, F, kp, partial);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
         const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
+        if constexpr (MODE == kForward) {
+            if (up) {
+                k_gather_update<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial,
+                                                                        m->lumped, up->rho, up->dt, up->u,
+                                                                        up->mask, up->rhs, up->u_new);
+                err = hipGetLastError();
+                return err == hipSuccess ? NSASM_OK : hip_fail(err, "update kernel launch");
+            }
+        }
         k_gather_partials<T, NOUT><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial, out,
                                                                         accumulate ? 1 : 0);
     } else if (m->scatter == NSASM_SCATTER_PATCH) {
-        k_assemble_patch<T, EDDY, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
+        k_assemble_patch<T, EDDY, CONV, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
             m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
             m->ref_slot, m->elem_pos, m->x, F, kp, out);
     } else {
         const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
-        k_assemble_atomic<T, EDDY, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x, F, kp,
-                                                                             out);
+        k_assemble_atomic<T, EDDY, CONV, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x, F,
+                                                                                   kp, out);
     }
     hipError_t err = hipGetLastError();
     return err == hipSuccess ? NSASM_OK : hip_fail(err, "assembly kernel launch");
+}
+
+template <typename T, int CONV, int MODE>
+nsasm_status launch_eddy(const nsasm_mesh *m, const nsasm_params &p, const KParams<T> &kp, NodeFields<T> F, T *o,
+                         const Update<T> *up, hipStream_t s) {
+    const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
+    if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
+        return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, s);
+    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, CONV, MODE>(m, kp, F, o, accumulate, up, s);
+    return launch<T, kNoEddy, CONV, MODE>(m, kp, F, o, accumulate, up, s);
+}
+
+// Physics selection (convective form, eddy viscosity) of a launch.
+template <typename T, int MODE>
+nsasm_status dispatch(const nsasm_mesh *m, const nsasm_params &p, NodeFields<T> F, T *o, const Update<T> *up,
+                    hipStream_t s) {
+    const KParams<T> kp = kernel_params<T>(p);
+    if constexpr (MODE == kVjpP) {
+        // the pressure term depends on neither the viscosity nor the convective form
+        return launch<T, kNoEddy, kAdvective, MODE>(m, kp, F, o, (p.flags & NSASM_ACCUMULATE) != 0, up, s);
+    } else {
+        if (p.convective_form != NSASM_CONVECTIVE_ADVECTIVE) return launch_eddy<T, kGeneral, MODE>(m, p, kp, F, o, up, s);
+        return launch_eddy<T, kAdvective, MODE>(m, p, kp, F, o, up, s);
+    }
+}
+
+template <typename T>
+nsasm_status fill_zero(T *o, int64_t n, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    k_fill_zero<T><<<static_cast<unsigned>(blocks), kThreads, 0, s>>>(o, n);
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, "fill kernel launch");
 }
 
 template <typename T, int MODE>
 nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *fa, const void *fb, const void *fc,
                  void *out, hipStream_t s) {
     T *o = static_cast<T *>(out);
-    const int64_t n_out = Fields<MODE>::NOUT * m->n_nodes;
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     // the gather kernel writes every node, so it needs no zero-fill
-    if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER) {
-        const int64_t blocks = std::min<int64_t>((n_out + kThreads - 1) / kThreads, 4096);
-        k_fill_zero<T><<<static_cast<unsigned>(blocks), kThreads, 0, s>>>(o, n_out);
-        hipError_t err = hipGetLastError();
-        if (err != hipSuccess) return hip_fail(err, "fill kernel launch");
-    }
-    const KParams<T> kp = kernel_params<T>(p);
+    if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER)
+        NSASM_TRY(fill_zero(o, Fields<MODE>::NOUT * m->n_nodes, s));
     const NodeFields<T> F{static_cast<const T *>(fa), static_cast<const T *>(fb), static_cast<const T *>(fc)};
-    if constexpr (MODE == kVjpP) {
-        return launch<T, kNoEddy, MODE>(m, kp, F, o, accumulate, s);  // the pressure term has no viscosity
-    } else {
-        if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
-            return launch<T, kVreman, MODE>(m, kp, F, o, accumulate, s);
-        if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, MODE>(m, kp, F, o, accumulate, s);
-        return launch<T, kNoEddy, MODE>(m, kp, F, o, accumulate, s);
-    }
+    return dispatch<T, MODE>(m, p, F, o, nullptr, s);
+}
+
+// Forward assembly and the explicit update: fused into the gather kernel with
+// the gather scatter, else assembled into `rhs` and updated by k_update.
+template <typename T>
+nsasm_status run_update(const nsasm_mesh *m, const nsasm_params &p, double dt, const void *u, const void *pr,
+                        const uint8_t *mask, void *rhs, void *u_new, hipStream_t s) {
+    const NodeFields<T> F{static_cast<const T *>(u), nullptr, static_cast<const T *>(pr)};
+    T *r = static_cast<T *>(rhs);
+    const Update<T> up{p.rho, dt, static_cast<const T *>(u), mask, r, static_cast<T *>(u_new)};
+    if (m->scatter == NSASM_SCATTER_PATCH_GATHER) return dispatch<T, kForward>(m, p, F, nullptr, &up, s);
+    NSASM_TRY(fill_zero(r, 3 * m->n_nodes, s));
+    NSASM_TRY((dispatch<T, kForward>(m, p, F, r, nullptr, s)));
+    const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
+    k_update<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, r, m->lumped, p.rho, dt, up.u, mask, up.u_new);
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, "update kernel launch");
 }
 
 // One device array argument of an entry point: name, pointer, components per
@@ -633,7 +807,51 @@ nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precis
     return st;
 }
 
+nsasm_status update_entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, double dt,
+                          const void *u, const void *p, const uint8_t *mask, void *rhs, void *u_new, void *stream) {
+    if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    NSASM_TRY(check_params(params));
+    if (params->flags != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "flags must be 0 for the explicit update");
+    if (prec != NSASM_FP64 && prec != NSASM_MIXED)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown precision %d", static_cast<int>(prec));
+    if (!std::isfinite(dt)) return fail(NSASM_ERR_INVALID_ARGUMENT, "dt must be finite");
+    const size_t es = (prec == NSASM_FP64) ? sizeof(double) : sizeof(float);
+    const size_t vec = 3 * es * m->n_nodes, sca = es * m->n_nodes, mb = static_cast<size_t>(m->n_nodes);
+    NSASM_TRY(check_device_ptr(u, "u"));
+    NSASM_TRY(check_device_ptr(p, "p"));
+    NSASM_TRY(check_device_ptr(u_new, "u_new"));
+    if (mask) NSASM_TRY(check_device_ptr(mask, "dirichlet_mask"));
+    if (rhs) {
+        NSASM_TRY(check_device_ptr(rhs, "rhs"));
+    } else if (m->scatter != NSASM_SCATTER_PATCH_GATHER) {
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "rhs is required unless the mesh uses the gather scatter");
+    }
+    if (u_new != u && overlaps(u_new, vec, u, vec))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "u_new must be u itself or not overlap it");
+    if (overlaps(u_new, vec, p, sca) || (mask && overlaps(u_new, vec, mask, mb)))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "u_new overlaps p or dirichlet_mask");
+    if (rhs && (overlaps(rhs, vec, u, vec) || overlaps(rhs, vec, p, sca) || overlaps(rhs, vec, u_new, vec) ||
+                (mask && overlaps(rhs, vec, mask, mb))))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "rhs overlaps another argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const nsasm_status st = (prec == NSASM_FP64) ? run_update<double>(m, *params, dt, u, p, mask, rhs, u_new, s)
+                                                 : run_update<float>(m, *params, dt, u, p, mask, rhs, u_new, s);
+    if (st == NSASM_OK) clear_error();
+    return st;
+}
+
 }  // namespace
+
+// V^L_n = sum over elements containing n of V_e / 4, in mesh order, through
+// the mesh's own scatter (deterministic with the gather scatter).
+nsasm_status compute_lumped_volume(nsasm_mesh *m, hipStream_t s) {
+    NSASM_TRY(device_alloc(&m->lumped, static_cast<size_t>(m->n_nodes), "lumped volume"));
+    if (m->scatter != NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(fill_zero(m->lumped, m->n_nodes, s));
+    const KParams<double> kp{};
+    const NodeFields<double> F{nullptr, nullptr, nullptr};
+    return launch<double, kNoEddy, kAdvective, kMass>(m, kp, F, m->lumped, false, nullptr, s);
+}
+
 }  // namespace nsasm
 
 extern "C" nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
@@ -666,4 +884,11 @@ extern "C" nsasm_status nsasm_assemble_rhs_jvp(const nsasm_mesh *mesh, const nsa
     using namespace nsasm;
     return entry<kJvp>(mesh, params, precision, {"u", u, 3, false}, {"du", du, 3, false}, {"dp", dp, 1, true},
                        {"drhs", drhs, 3, false}, stream);
+}
+
+extern "C" nsasm_status nsasm_explicit_update(const nsasm_mesh *mesh, const nsasm_params *params,
+                                              nsasm_precision precision, double dt, const void *u, const void *p,
+                                              const uint8_t *dirichlet_mask, void *rhs, void *u_new,
+                                              void *stream) {
+    return nsasm::update_entry(mesh, params, precision, dt, u, p, dirichlet_mask, rhs, u_new, stream);
 }

@@ -78,6 +78,8 @@ struct nsasm_mesh {
     int32_t *node_ref_off = nullptr;  // [n_nodes + 1] each node's run in the partial buffer
     int32_t *ref_slot = nullptr;      // [patch_node_refs] node-major position of each patch reference
     double *partial = nullptr;        // [3 * patch_node_refs] partial sums (float or double)
+
+    double *lumped = nullptr;         // [n_nodes] lumped volume V^L, mesh order
 };
 
 namespace nsasm {
@@ -93,6 +95,10 @@ nsasm_status radix_sort_pairs_u32(uint32_t *keys, int32_t *vals, int64_t n, int 
 // (host, after a synchronisation) if total != nullptr.
 nsasm_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total,
                                 hipStream_t stream);
+
+// Fill m->lumped (allocated here) with the lumped volume of every node
+// (assemble.hip); asynchronous on `stream`.
+nsasm_status compute_lumped_volume(nsasm_mesh *m, hipStream_t stream);
 
 // Grid of `n_tiles` workgroups padded to a multiple of the XCD count; see xcd_tile().
 inline unsigned xcd_grid(int64_t n_tiles) {

@@ -323,6 +323,7 @@ void free_mesh(nsasm_mesh *m) {
     device_free(m->node_ref_off);
     device_free(m->ref_slot);
     device_free(m->partial);
+    device_free(m->lumped);
     delete m;
 }
 
@@ -541,6 +542,7 @@ nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64
             return st;
         }
     }
+    NSASM_TRY(compute_lumped_volume(m, stream));
     NSASM_HIP(hipStreamSynchronize(stream));
     clear_error();
     return NSASM_OK;
@@ -679,4 +681,14 @@ extern "C" nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t nc
                                               nsasm_precision precision, const void *mesh_ordered,
                                               void *user, void *stream) {
     return nsasm::reorder_entry(mesh, ncomp, precision, mesh_ordered, user, stream, false);
+}
+
+extern "C" nsasm_status nsasm_mesh_lumped_volume(const nsasm_mesh *mesh, double *lumped, void *stream) {
+    using namespace nsasm;
+    if (!mesh) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
+    NSASM_TRY(check_device_ptr(lumped, "lumped"));
+    NSASM_HIP(hipMemcpyAsync(lumped, mesh->lumped, sizeof(double) * mesh->n_nodes, hipMemcpyDeviceToDevice,
+                             static_cast<hipStream_t>(stream)));
+    clear_error();
+    return NSASM_OK;
 }

@@ -27,18 +27,20 @@ class Case:
     cs: float = 0.0
     rho: float = 1.0
     model: str = "smagorinsky"
+    form: str = "advective"
 
     def params(self):
         from paper_2403_08777_amd import api
 
-        return api.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, self.model)
+        return api.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, self.model, self.form)
 
     def oracle_params(self):
-        return oracle.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, model=self.model)
+        return oracle.Params(self.rho, self.mu, self.cs, synth.BODY_FORCE, model=self.model, form=self.form)
 
     def label(self):
         m = "" if self.model == "smagorinsky" else f" {self.model}"
-        return f"n={self.n} jit={self.jitter} perm={self.permute} mu={self.mu} cs={self.cs}{m}"
+        f = "" if self.form == "advective" else f" {self.form}"
+        return f"n={self.n} jit={self.jitter} perm={self.permute} mu={self.mu} cs={self.cs}{m}{f}"
 
 
 class Prepared:

@@ -44,8 +44,9 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stdio.h>
 #include "nsasm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(nsasm_params), offsetof(nsasm_params, body_force),
-         offsetof(nsasm_params, flags), offsetof(nsasm_params, eddy_model));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(nsasm_params), offsetof(nsasm_params, body_force),
+         offsetof(nsasm_params, flags), offsetof(nsasm_params, eddy_model),
+         offsetof(nsasm_params, convective_form), offsetof(nsasm_params, reserved));
   printf("%zu %zu %zu\n", sizeof(nsasm_mesh_options), offsetof(nsasm_mesh_options, scatter),
          offsetof(nsasm_mesh_options, patch_elems));
   printf("%zu %zu %zu\n", sizeof(nsasm_mesh_info_t), offsetof(nsasm_mesh_info_t, scatter),
@@ -58,7 +59,7 @@ int main(void) {
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     p = [int(v) for v in lines[0].split()]
     assert p == [ctypes.sizeof(api._Params), api._Params.body_force.offset, api._Params.flags.offset,
-                 api._Params.eddy_model.offset]
+                 api._Params.eddy_model.offset, api._Params.convective_form.offset, api._Params.reserved.offset]
     o = [int(v) for v in lines[1].split()]
     assert o == [ctypes.sizeof(api._MeshOptions), api._MeshOptions.scatter.offset,
                  api._MeshOptions.patch_elems.offset]

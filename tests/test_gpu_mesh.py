@@ -174,6 +174,16 @@ def test_bad_arguments_on_device():
     st = lib.nsasm_assemble_rhs_vjp(pr.mesh.handle, ctypes.byref(prm_bad), 0, u.data_ptr(), lam.data_ptr(),
                                     out.data_ptr(), None)
     assert st == 1 and b"eddy_model" in lib.nsasm_last_error()
+    prm_bad = pr.case.params().c_struct()
+    prm_bad.convective_form = 5
+    st = lib.nsasm_assemble_rhs_jvp(pr.mesh.handle, ctypes.byref(prm_bad), 0, u.data_ptr(), lam.data_ptr(), None,
+                                    out.data_ptr(), None)
+    assert st == 1 and b"convective_form" in lib.nsasm_last_error()
+    prm_bad = pr.case.params().c_struct()
+    prm_bad.reserved = 1
+    st = lib.nsasm_assemble_rhs(pr.mesh.handle, ctypes.byref(prm_bad), 0, u.data_ptr(), p.data_ptr(),
+                                out.data_ptr(), None)
+    assert st == 1 and b"reserved" in lib.nsasm_last_error()
     # the mesh still works after the failures
     assert oracle.rel_l2(pr.rhs(), pr.oracle_rhs()) <= 1e-12
 

@@ -1,0 +1,142 @@
+"""Explicit-update epilogue on the GPU: the lumped volume and one explicit
+momentum stage (u + dt R / (rho V^L), Dirichlet mask) against the oracle, in
+every scatter mode, fused (gather scatter) and unfused, in place and out of
+place, FP64 and mixed, at small and full size; and the entry point's
+argument checks."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2403_08777_amd import synth
+from tests.gpu_helpers import Case, Prepared, log
+
+pytestmark = pytest.mark.gpu
+
+CASES = [Case(7, jitter=True, permute=True, mu=1e-3),
+         Case(9, jitter=True, permute=True, mu=1e-4, cs=0.1, model="vreman", form="skew"),
+         Case(5, jitter=False, permute=False, mu=1e-3, cs=0.1)]
+DT = 3e-3
+
+
+def _mask(pr):
+    return np.random.default_rng(31).integers(0, 8, pr.m.n_nodes).astype(np.uint8)
+
+
+def _fixed(mask):
+    return np.stack([(mask >> i) & 1 for i in range(3)], axis=1).astype(bool)
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+@pytest.mark.parametrize("case", CASES, ids=[c.label() for c in CASES])
+def test_lumped_volume(case, scatter):
+    pr = Prepared(case, scatter=scatter)
+    got = pr.mesh.from_mesh_order(pr.mesh.lumped_volume()).cpu().numpy()
+    ref = oracle.lumped_volume(pr.m.coords, pr.m.conn)
+    err = float(np.max(np.abs(got - ref) / ref))
+    log(f"lumped {case.label()} {scatter}: max rel {err:.2e}")
+    assert err <= 1e-14
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+@pytest.mark.parametrize("case", CASES, ids=[c.label() for c in CASES])
+def test_update_fp64(case, scatter):
+    from paper_2403_08777_amd import api
+
+    log(f"update fp64 {case.label()} {scatter}")
+    pr = Prepared(case, scatter=scatter)
+    u, p, _ = pr.fields(torch.float64)
+    mask_np = _mask(pr)
+    mask = pr.mesh.to_mesh_order(torch.from_numpy(mask_np.astype(np.float64)).to(pr.dev)).to(torch.uint8)
+    prm = case.params()
+    ref, ref_r = oracle.explicit_update(pr.m.coords, pr.m.conn, pr.u, pr.p, case.oracle_params(), DT, mask_np)
+    back = lambda t: pr.mesh.from_mesh_order(t).cpu().numpy()
+    rhs = torch.empty_like(u)
+    un = back(api.explicit_update(pr.mesh, u, p, prm, DT, mask, rhs=rhs))
+    fixed = _fixed(mask_np)
+    assert np.array_equal(un[fixed], pr.u[fixed])
+    e_inc = oracle.rel_l2(un - pr.u, ref - pr.u)
+    e_rhs = oracle.rel_l2(back(rhs), ref_r)
+    # in place, no mask, no rhs output (fused with the gather scatter)
+    uu = u.clone()
+    api.explicit_update(pr.mesh, uu, p, prm, DT, out=uu)
+    ref0, _ = oracle.explicit_update(pr.m.coords, pr.m.conn, pr.u, pr.p, case.oracle_params(), DT)
+    e_inp = oracle.rel_l2(back(uu) - pr.u, ref0 - pr.u)
+    log(f"  increment {e_inc:.2e} rhs {e_rhs:.2e} in-place {e_inp:.2e}")
+    assert e_inc <= 1e-12 and e_rhs <= 1e-12 and e_inp <= 1e-12
+    if scatter == "patch_gather":
+        # the fused path's rhs is the forward's, bit for bit (same kernels, same order)
+        assert torch.equal(rhs, api.assemble_rhs(pr.mesh, u, p, prm))
+
+
+def test_update_mixed():
+    from paper_2403_08777_amd import api
+
+    case = Case(16, jitter=True, permute=True, mu=1e-4, cs=0.1, form="emac")
+    pr = Prepared(case)
+    u, p, _ = pr.fields(torch.float32)
+    mask_np = _mask(pr)
+    mask = pr.mesh.to_mesh_order(torch.from_numpy(mask_np.astype(np.float32)).to(pr.dev)).to(torch.uint8)
+    un = pr.mesh.from_mesh_order(api.explicit_update(pr.mesh, u, p, case.params(), DT, mask)).double().cpu().numpy()
+    ref, _ = oracle.explicit_update(pr.m.coords, pr.m.conn, pr.u, pr.p, case.oracle_params(), DT, mask_np)
+    u32 = pr.u.astype(np.float32).astype(np.float64)
+    fixed = _fixed(mask_np)
+    assert np.array_equal(un[fixed], u32[fixed])
+    err = oracle.rel_l2(un - u32, ref - pr.u)
+    log(f"update mixed {case.label()}: increment {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_update_full_size():
+    """96^3 jittered benchmark mesh, fused update in place with a boundary
+    Dirichlet mask (all three components on the cube faces)."""
+    from paper_2403_08777_amd import api
+
+    wl = synth.WORKLOADS["cube96_jit_perm"]
+    m, u, p, _ = synth.build(wl)
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev))
+    bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
+    mask_np = np.where(bnd, 7, 0).astype(np.uint8)
+    tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    ut = tm(u)
+    mask = tm(mask_np.astype(np.float64)).to(torch.uint8)
+    prm = api.Params(wl.rho, wl.mu, wl.cs, wl.body_force)
+    api.explicit_update(mesh, ut, tm(p), prm, DT, mask, out=ut)
+    un = mesh.from_mesh_order(ut).cpu().numpy()
+    ref, _ = oracle.explicit_update(m.coords, m.conn, u, p, oracle.Params(wl.rho, wl.mu, wl.cs, wl.body_force),
+                                    DT, mask_np)
+    assert np.array_equal(un[bnd], u[bnd])
+    err = oracle.rel_l2(un - u, ref - u)
+    log(f"update 96^3 in place: increment {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_update_argument_checks():
+    from paper_2403_08777_amd import api
+
+    case = Case(4, jitter=True, permute=True)
+    pr = Prepared(case, scatter="atomic")
+    lib = api.lib
+    u, p, _ = pr.fields(torch.float64)
+    out = torch.empty_like(u)
+    rhs = torch.empty_like(u)
+    prm = case.params().c_struct()
+    h = pr.mesh.handle
+    call = lambda prm_, dt, uu, rr, oo: lib.nsasm_explicit_update(h, ctypes.byref(prm_), 0, dt, uu, p.data_ptr(),
+                                                                  None, rr, oo, None)
+    # atomic scatter: rhs is required as workspace
+    assert call(prm, DT, u.data_ptr(), None, out.data_ptr()) == 1 and b"rhs" in lib.nsasm_last_error()
+    assert call(prm, float("nan"), u.data_ptr(), rhs.data_ptr(), out.data_ptr()) == 1
+    acc = case.params().c_struct(accumulate=True)
+    assert call(acc, DT, u.data_ptr(), rhs.data_ptr(), out.data_ptr()) == 1 and b"flags" in lib.nsasm_last_error()
+    # partial overlap of u_new with u, rhs aliasing u
+    big = torch.empty(3 * pr.m.n_nodes + 3, dtype=torch.float64, device=pr.dev)
+    assert call(prm, DT, big.data_ptr(), rhs.data_ptr(), big.data_ptr() + 8) == 1
+    assert call(prm, DT, u.data_ptr(), u.data_ptr(), out.data_ptr()) == 1
+    # a valid call still works afterwards
+    assert call(prm, DT, u.data_ptr(), rhs.data_ptr(), out.data_ptr()) == 0
+    torch.cuda.synchronize()
