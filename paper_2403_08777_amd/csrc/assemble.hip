@@ -195,9 +195,9 @@ __device__ inline T eddy_viscosity(const T (&G)[3][3], T vol, T rho_c, T (&D)[3]
     return c * s;
 }
 
-template <typename T, int EDDY, int CONV>
+template <typename T, int EDDY, int CONV, typename Sink>
 __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&pe)[4],
-                                   const KParams<T> &P, T (&re)[4][3]) {
+                                   const KParams<T> &P, Sink &&emit) {
     T G[3][3];
     vector_gradient(gN, ue, G);
     T q[3];
@@ -226,18 +226,20 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
             z[j] = sc * (ue[a][j] + U[j]);
             y[j] = z[j] + sv * gN[a][j];
         }
+        T re[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            re[a][i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
+            re[i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
             if (CONV == kGeneral)
-                re[a][i] -= at * z[i] + P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
+                re[i] -= at * z[i] + P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
         }
+        emit(a, re);
     }
 }
 
-template <typename T, int EDDY, int CONV>
+template <typename T, int EDDY, int CONV, typename Sink>
 __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
-                                   const KParams<T> &P, T (&ge)[4][3]) {
+                                   const KParams<T> &P, Sink &&emit) {
     T G[3][3], Lam[3][3];
     vector_gradient(gN, ue, G);
     vector_gradient(gN, le, Lam);
@@ -296,6 +298,7 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const T w0 = le[b][0] + L[0], w1 = le[b][1] + L[1], w2 = le[b][2] + L[2];
+        T ge[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             // (K^T w)_k = (G^T w)_k + conv_a tr(G) w_k + conv_b (G w)_k
@@ -304,31 +307,35 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
                 const T wk = (k == 0) ? w0 : (k == 1) ? w1 : w2;
                 kw += at * wk + P.conv_b * (G[k][0] * w0 + G[k][1] * w1 + G[k][2] * w2);
             }
-            ge[b][k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw;
+            ge[k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw;
         }
+        emit(b, ge);
     }
 }
 
 // Pressure VJP: the pressure term -(V/4) q at every vertex is linear in p,
 // so lambda . R^p = -(V/4) L . q with L = sum_a lambda_a and
 // d/dp_b = -(V/4) L . grad N_b.
-template <typename T>
-__device__ inline void element_vjp_p(const T (&gN)[4][3], T vol, const T (&le)[4][3], T (&gp)[4][3]) {
+template <typename T, typename Sink>
+__device__ inline void element_vjp_p(const T (&gN)[4][3], T vol, const T (&le)[4][3], Sink &&emit) {
     const T w = -vol * T(0.25);
     T L[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) L[i] = le[0][i] + le[1][i] + le[2][i] + le[3][i];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) gp[b][0] = w * (L[0] * gN[b][0] + L[1] * gN[b][1] + L[2] * gN[b][2]);
+    for (int b = 0; b < 4; ++b) {
+        const T gp[3] = {w * (L[0] * gN[b][0] + L[1] * gN[b][1] + L[2] * gN[b][2]), T(0), T(0)};
+        emit(b, gp);
+    }
 }
 
 // JVP: directional derivative of R^e_a = b - G y_a along (du, dp):
 //   dR^e_a = -(V/4) dq - dG y_a - G dy_a,
 //   dy_a = (rho V / 20)(du_a + dU) + V (D : dG) grad N_a,
 // with dG = grad du, dq = grad dp and D = d mu_t / d G.
-template <typename T, int EDDY, int CONV>
+template <typename T, int EDDY, int CONV, typename Sink>
 __device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&due)[4][3],
-                                   const T (&dpe)[4], const KParams<T> &P, T (&dr)[4][3]) {
+                                   const T (&dpe)[4], const KParams<T> &P, Sink &&emit) {
     T G[3][3], dG[3][3], dq[3];
     vector_gradient(gN, ue, G);
     vector_gradient(gN, due, dG);
@@ -368,30 +375,35 @@ __device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][
             y[j] = z[j] + sv * gN[a][j];
             dy[j] = dz[j] + dsv * gN[a][j];
         }
+        T dr[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            dr[a][i] = -w4 * dq[i] - (dG[i][0] * y[0] + dG[i][1] * y[1] + dG[i][2] * y[2]) -
-                       (G[i][0] * dy[0] + G[i][1] * dy[1] + G[i][2] * dy[2]);
+            dr[i] = -w4 * dq[i] - (dG[i][0] * y[0] + dG[i][1] * y[1] + dG[i][2] * y[2]) -
+                    (G[i][0] * dy[0] + G[i][1] * dy[1] + G[i][2] * dy[2]);
             if (CONV == kGeneral)
-                dr[a][i] -= dat * z[i] + at * dz[i] +
+                dr[i] -= dat * z[i] + at * dz[i] +
                             P.conv_b * (dG[0][i] * z[0] + dG[1][i] * z[1] + dG[2][i] * z[2] +
                                         G[0][i] * dz[0] + G[1][i] * dz[1] + G[2][i] * dz[2]);
         }
+        emit(a, dr);
     }
 }
 
-// The element operation of a launch mode on gathered vertex data.
-template <typename T, int EDDY, int CONV, int MODE>
+// The element operation of a launch mode on gathered vertex data.  Each
+// vertex's contribution is handed to emit(a, value[3]) as soon as it is
+// known, so that it need not stay in registers until the element is done.
+template <typename T, int EDDY, int CONV, int MODE, typename Sink>
 __device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3], const T (&eb)[4][3],
-                                  const T (&ec)[4], const KParams<T> &P, T (&r)[4][3]) {
-    if (MODE == kForward) element_rhs<T, EDDY, CONV>(gN, vol, ea, ec, P, r);
-    if (MODE == kVjp) element_vjp<T, EDDY, CONV>(gN, vol, ea, eb, P, r);
-    if (MODE == kVjpP) element_vjp_p(gN, vol, eb, r);
-    if (MODE == kJvp) element_jvp<T, EDDY, CONV>(gN, vol, ea, eb, ec, P, r);
-    if (MODE == kMass) {
+                                  const T (&ec)[4], const KParams<T> &P, Sink &&emit) {
+    if constexpr (MODE == kForward) element_rhs<T, EDDY, CONV>(gN, vol, ea, ec, P, emit);
+    if constexpr (MODE == kVjp) element_vjp<T, EDDY, CONV>(gN, vol, ea, eb, P, emit);
+    if constexpr (MODE == kVjpP) element_vjp_p(gN, vol, eb, emit);
+    if constexpr (MODE == kJvp) element_jvp<T, EDDY, CONV>(gN, vol, ea, eb, ec, P, emit);
+    if constexpr (MODE == kMass) {
         // row-sum lumping of the P1 mass matrix: sum_b int N_a N_b = V/4
+        const T w[3] = {vol * T(0.25), T(0), T(0)};
 #pragma unroll
-        for (int a = 0; a < 4; ++a) r[a][0] = vol * T(0.25);
+        for (int a = 0; a < 4; ++a) emit(a, w);
     }
 }
 
@@ -448,12 +460,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
     tet_geometry(xe, g64, vol64);
     T gN[4][3], vol;
     to_field(g64, vol64, gN, vol);
-    T r[4][3];
-    element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, r);
+    element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, [&](int a, const T (&r)[3]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int i = 0; i < FL::NOUT; ++i) global_add(&out[FL::NOUT * ids[a] + i], r[a][i]);
+        for (int i = 0; i < FL::NOUT; ++i) global_add(&out[FL::NOUT * ids[a] + i], r[i]);
+    });
 }
 
 // One workgroup per patch (see the file header).  LDS holds the patch's
@@ -465,9 +475,9 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
 // (position ref_slot of the patch reference), for k_gather_partials.
 template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_assemble_patch(
-    int64_t ne, int64_t np, int32_t patch_elems, const int32_t *__restrict__ patch_off,
-    const int32_t *__restrict__ patch_nodes, const int32_t *__restrict__ patch_node_start,
-    const int32_t *__restrict__ ref_slot, const ushort4 *__restrict__ elem_pos, const double *__restrict__ x,
+    int64_t ne, int64_t np, int32_t patch_elems, int32_t stride, const int2 *__restrict__ patch_rec,
+    const int32_t *__restrict__ patch_ref, const ushort4 *__restrict__ elem_pos,
+    const uchar4 *__restrict__ elem_loc, const double *__restrict__ x,
     NodeFields<T> F, KParams<T> P, T *__restrict__ out) {
     using FL = Fields<MODE>;
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
@@ -475,7 +485,6 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
-    __shared__ uint8_t node_of_slot[kS];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
     T(*sval)[kS] = reinterpret_cast<T(*)[kS]>(smem);
@@ -483,36 +492,42 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
     if (patch >= np) return;
     const int t = threadIdx.x;
-    const int32_t beg = patch_off[patch];
-    const int32_t cnt = patch_off[patch + 1] - beg;
     const int64_t first = patch * static_cast<int64_t>(patch_elems);
     const int nel = static_cast<int>(min<int64_t>(patch_elems, ne - first));
     ushort4 pos = make_ushort4(0, 0, 0, 0);
-    if (t < nel) pos = elem_pos[first + t];
-    int64_t node = 0;
+    uchar4 loc = make_uchar4(0, 0, 0, 0);
+    if (t < nel) {
+        pos = elem_pos[first + t];
+        loc = elem_loc[first + t];
+    }
+    // every load of the patch's description is independent of the others
+    int64_t node = -1;
     int32_t slot = 0, s_beg = 0, s_end = 0;
-    if (t < cnt) {
-        node = patch_nodes[beg + t];
-        s_beg = patch_node_start[beg + t];
-        s_end = (t + 1 < cnt) ? patch_node_start[beg + t + 1] : 4 * nel;
-        if (GATHER) slot = ref_slot[beg + t];
+    int lp = 0;  // the node's position in the LDS node arrays
+    if (t < stride) {
+        const int2 rec = patch_rec[patch * stride + t];
+        node = rec.x;
+        s_beg = rec.y & 0x7ff;
+        s_end = (rec.y >> 11) & 0x7ff;
+        lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);
+        if (GATHER) slot = patch_ref[patch * stride + t];
+    }
+    const bool has_node = node >= 0;
+    if (has_node) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            sx[i][t] = x[3 * node + i];
-            if (FL::NA) sf[i][t] = F.fa[3 * node + i];
-            if (FL::NB) sf[FL::NA + i][t] = F.fb[3 * node + i];
+            sx[i][lp] = x[3 * node + i];
+            if (FL::NA) sf[i][lp] = F.fa[3 * node + i];
+            if (FL::NB) sf[FL::NA + i][lp] = F.fb[3 * node + i];
         }
-        if (FL::NC) sf[FL::NA + FL::NB][t] = F.fc ? F.fc[node] : T(0);
-        for (int k = s_beg; k < s_end; ++k) node_of_slot[k] = static_cast<uint8_t>(t);
+        if (FL::NC) sf[FL::NA + FL::NB][lp] = F.fc ? F.fc[node] : T(0);
     }
     __syncthreads();
 
     T r[4][3];
     const int sl[4] = {pos.x, pos.y, pos.z, pos.w};
     if (t < nel) {
-        int la[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) la[a] = node_of_slot[sl[a]];
+        const int la[4] = {loc.x, loc.y, loc.z, loc.w};
         double xe[4][3];
         T ea[4][3] = {}, eb[4][3] = {}, ec[4] = {};
 #pragma unroll
@@ -529,7 +544,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
         tet_geometry(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
-        element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, r);
+        element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, [&](int a, const T (&v)[3]) {
+#pragma unroll
+            for (int i = 0; i < FL::NOUT; ++i) r[a][i] = v[i];
+        });
     }
     __syncthreads();  // node data is dead from here on; its bytes become slots
     if (t < nel) {
@@ -539,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
             for (int i = 0; i < FL::NOUT; ++i) sval[i][sl[a]] = r[a][i];
     }
     __syncthreads();
-    if (t < cnt) {
+    if (has_node) {
         T acc[FL::NOUT];
 #pragma unroll
         for (int i = 0; i < FL::NOUT; ++i) acc[i] = T(0);
@@ -683,8 +701,8 @@ nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, 
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
         T *partial = reinterpret_cast<T *>(m->partial);
         k_assemble_patch<T, EDDY, CONV, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
-            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
-            m->ref_slot, m->elem_pos, m->x, F, kp, partial);
+            m->n_elems, m->n_patches, m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
+            m->elem_loc, m->x, F, kp, partial);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
         const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
@@ -701,8 +719,8 @@ nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, 
                                                                         accumulate ? 1 : 0);
     } else if (m->scatter == NSASM_SCATTER_PATCH) {
         k_assemble_patch<T, EDDY, CONV, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
-            m->n_elems, m->n_patches, m->patch_elems, m->patch_off, m->patch_nodes, m->patch_node_start,
-            m->ref_slot, m->elem_pos, m->x, F, kp, out);
+            m->n_elems, m->n_patches, m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
+            m->elem_loc, m->x, F, kp, out);
     } else {
         const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
         k_assemble_atomic<T, EDDY, CONV, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x, F,

@@ -64,20 +64,29 @@ struct nsasm_mesh {
     int4 *conn = nullptr;         // [n_elems] mesh node ids, mesh element order
     double *x = nullptr;          // [n_nodes * 3] coordinates, mesh order
 
-    // element patches (scatter == PATCH)
+    // element patches (scatter == PATCH or PATCH_GATHER)
     int32_t n_patches = 0;
     int32_t patch_elems = 0;
     int32_t max_patch_nodes = 0;
+    int32_t patch_stride = 0;       // entries per patch in patch_rec / patch_ref (>= max_patch_nodes)
     int64_t patch_node_refs = 0;
-    int32_t *patch_off = nullptr;   // [n_patches + 1] offsets into patch_nodes
-    int32_t *patch_nodes = nullptr;        // distinct mesh node ids of each patch, ascending
-    int32_t *patch_node_start = nullptr;   // first slot of each patch node (same indexing, +1 padding)
-    ushort4 *elem_pos = nullptr;           // [n_elems] slot of each (element, vertex)
+    // [n_patches * patch_stride]: the patch's distinct nodes, ascending, as
+    // {mesh node id, first slot | end slot << 11 | LDS position << 22};
+    // {-1, 0} pads each patch
+    int2 *patch_rec = nullptr;
+    ushort4 *elem_pos = nullptr;    // [n_elems] slot of each (element, vertex)
+    uchar4 *elem_loc = nullptr;     // [n_elems] LDS position of each vertex's node in its patch
 
     // deterministic gather of per-patch partial sums (scatter == PATCH_GATHER)
     int32_t *node_ref_off = nullptr;  // [n_nodes + 1] each node's run in the partial buffer
-    int32_t *ref_slot = nullptr;      // [patch_node_refs] node-major position of each patch reference
+    int32_t *patch_ref = nullptr;     // as patch_rec: node-major partial-sum position of each entry
     double *partial = nullptr;        // [3 * patch_node_refs] partial sums (float or double)
+
+    // compact patch lists, used while the mesh is built and freed after
+    int32_t *patch_off = nullptr;          // [n_patches + 1] offsets into patch_nodes
+    int32_t *patch_nodes = nullptr;        // distinct mesh node ids of each patch, ascending
+    int32_t *patch_node_start = nullptr;   // first slot of each patch node (same indexing, +1 padding)
+    int32_t *ref_slot = nullptr;           // [patch_node_refs] node-major position of each reference
 
     double *lumped = nullptr;         // [n_nodes] lumped volume V^L, mesh order
 };

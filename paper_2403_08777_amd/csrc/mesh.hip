@@ -296,6 +296,136 @@ __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64
     }
 }
 
+// LDS placement of each patch node, chosen so that the element gathers of
+// the assembly kernels are free of LDS bank conflicts where possible.  An
+// assembly workgroup reads vertex a of its elements, lane = element, in one
+// instruction per field; the hardware serves lanes in groups, and two lanes
+// of a group that read different nodes whose LDS words fall in the same bank
+// wait for each other.  Node data sits in arrays indexed by the position, so
+// the bank of a node is its position modulo the bank count (in 4-byte words
+// for float fields, 8-byte pairs for double).  Nodes read together by a group
+// of 16, 32 or 64 consecutive elements (for one vertex slot) get positions
+// distinct modulo 16, 32 or 64, by greedy colouring in node order: class
+// c in [0, 64) with at most 4 nodes, position c + 64 * (rank in class).  When
+// no class satisfies every level the coarser levels are dropped in turn.
+// Any placement is correct; this one only saves LDS cycles.
+constexpr int kColorLevels = 3;           // groups of 64, 32, 16 lanes
+constexpr int kAdjWords = kMaxPatchNodes * kMaxPatchNodes / 32;
+
+__global__ __launch_bounds__(kThreads) void k_patch_color(const uint32_t *off, const int32_t *start,
+                                                           const ushort4 *elem_pos, int64_t ne, int elems,
+                                                           uint8_t *position, uchar4 *elem_loc) {
+    __shared__ uint32_t adj[kColorLevels][kAdjWords];  // 24 KB: adjacency bit matrices
+    __shared__ uint8_t node_of_slot[kPatchSlots];
+    __shared__ uint8_t la[4][kMaxPatchElems];
+    __shared__ uint8_t cls[kMaxPatchNodes];
+    __shared__ uint8_t posn[kMaxPatchNodes];
+    __shared__ uint32_t used[64];
+    const int64_t p = blockIdx.x;
+    const int t = threadIdx.x;
+    const uint32_t beg = off[p], cnt = off[p + 1] - beg;
+    const int64_t first = p * static_cast<int64_t>(elems);
+    const int nel = static_cast<int>(min<int64_t>(elems, ne - first));
+    for (int k = t; k < kColorLevels * kAdjWords; k += kThreads) (&adj[0][0])[k] = 0u;
+    if (t < 64) used[t] = 0u;
+    if (static_cast<uint32_t>(t) < cnt) {
+        const int sb = start[beg + t];
+        const int se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
+        for (int k = sb; k < se; ++k) node_of_slot[k] = static_cast<uint8_t>(t);
+    }
+    __syncthreads();
+    if (t < nel) {
+        const ushort4 ps = elem_pos[first + t];
+        la[0][t] = node_of_slot[ps.x];
+        la[1][t] = node_of_slot[ps.y];
+        la[2][t] = node_of_slot[ps.z];
+        la[3][t] = node_of_slot[ps.w];
+    }
+    __syncthreads();
+    if (t < nel) {
+#pragma unroll
+        for (int lvl = 0; lvl < kColorLevels; ++lvl) {
+            const int lanes = 64 >> lvl;
+            const int g0 = t & ~(lanes - 1);
+            const int g1 = min(g0 + lanes, nel);
+            for (int a = 0; a < 4; ++a) {
+                const int x = la[a][t];
+                for (int e = g0; e < g1; ++e) {
+                    const int y = la[a][e];
+                    if (y != x) atomicOr(&adj[lvl][(x * kMaxPatchNodes + y) >> 5], 1u << (y & 31));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // greedy colouring by the first wave, nodes in ascending order
+    if (t < 64) {
+        for (uint32_t x = 0; x < cnt; ++x) {
+            uint64_t m64 = 0;
+            uint32_t m32 = 0, m16 = 0;
+            for (int y = t; y < static_cast<int>(x); y += 64) {
+                const int c = cls[y];
+                const int w = (static_cast<int>(x) * kMaxPatchNodes + y) >> 5, b = y & 31;
+                if ((adj[0][w] >> b) & 1u) m64 |= uint64_t(1) << c;
+                if ((adj[1][w] >> b) & 1u) m32 |= 1u << (c & 31);
+                if ((adj[2][w] >> b) & 1u) m16 |= 1u << (c & 15);
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                m64 |= static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(m64), o, 64));
+                m32 |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(m32), o, 64));
+                m16 |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(m16), o, 64));
+            }
+            const int c = t;  // this lane's candidate class
+            const bool room = used[c] < 4u;
+            const bool f16 = (m16 >> (c & 15)) & 1u, f32 = (m32 >> (c & 31)) & 1u, f64 = (m64 >> c) & 1u;
+            uint64_t ok = __ballot(room && !f64 && !f32 && !f16);
+            if (!ok) ok = __ballot(room && !f32 && !f16);
+            if (!ok) ok = __ballot(room && !f32);
+            if (!ok) ok = __ballot(room);
+            const int choice = __ffsll(static_cast<long long>(ok)) - 1;
+            if (t == 0) {
+                const uint8_t pos = static_cast<uint8_t>(choice + 64 * used[choice]);
+                cls[x] = static_cast<uint8_t>(choice);
+                posn[x] = pos;
+                position[beg + x] = pos;
+                used[choice] += 1u;
+            }
+            // only the first wave runs this loop: make lane 0's LDS writes
+            // visible to the wave before the next node
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    if (t < nel)
+        elem_loc[first + t] = make_uchar4(posn[la[0][t]], posn[la[1][t]], posn[la[2][t]], posn[la[3][t]]);
+}
+
+// Fixed-stride patch records: entry t of patch p at p * stride + t, so an
+// assembly workgroup finds its nodes without first reading the patch offset.
+// rec.y packs the node's slot run [first, end) and its LDS position:
+// first | end << 11 | position << 22.
+__global__ __launch_bounds__(kThreads) void k_patch_pad(const uint32_t *off, const int32_t *nodes,
+                                                         const int32_t *start, const uint8_t *position,
+                                                         const int32_t *ref_slot, int64_t ne, int elems,
+                                                         int stride, int2 *rec, int32_t *ref) {
+    const int64_t p = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t >= stride) return;
+    const uint32_t beg = off[p], cnt = off[p + 1] - beg;
+    const int nel = static_cast<int>(min<int64_t>(elems, ne - p * elems));
+    int2 r = make_int2(-1, 0);
+    int32_t s = 0;
+    if (static_cast<uint32_t>(t) < cnt) {
+        const int sb = start[beg + t];
+        const int se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
+        r = make_int2(nodes[beg + t], sb | (se << 11) | (static_cast<int>(position[beg + t]) << 22));
+        if (ref_slot) s = ref_slot[beg + t];
+    }
+    rec[p * stride + t] = r;
+    if (ref) ref[p * stride + t] = s;
+}
+
 // Number of patch references of every node (patch_nodes entries equal to it).
 __global__ __launch_bounds__(kThreads) void k_count_refs(const int32_t *nodes, int64_t refs, uint32_t *count) {
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
@@ -320,11 +450,23 @@ void free_mesh(nsasm_mesh *m) {
     device_free(m->patch_nodes);
     device_free(m->patch_node_start);
     device_free(m->elem_pos);
+    device_free(m->elem_loc);
     device_free(m->node_ref_off);
     device_free(m->ref_slot);
+    device_free(m->patch_rec);
+    device_free(m->patch_ref);
     device_free(m->partial);
     device_free(m->lumped);
     delete m;
+}
+
+// Free the compact patch lists once the padded records exist.
+void free_compact_patches(nsasm_mesh *m) {
+    device_free(m->patch_off);
+    device_free(m->patch_nodes);
+    device_free(m->patch_node_start);
+    device_free(m->ref_slot);
+    m->patch_off = m->patch_nodes = m->patch_node_start = m->ref_slot = nullptr;
 }
 
 nsasm_status read_flags(const CreateFlags *d_flags, hipStream_t stream, CreateFlags *h) {
@@ -449,6 +591,38 @@ nsasm_status build_node_gather(nsasm_mesh *m, hipStream_t stream) {
     return NSASM_OK;
 }
 
+// Padded patch records (and partial-sum positions with the gather scatter)
+// from the compact lists, which are then freed.
+nsasm_status build_patch_records(nsasm_mesh *m, hipStream_t stream) {
+    const int stride = (m->max_patch_nodes + 7) / 8 * 8;
+    const size_t n = static_cast<size_t>(m->n_patches) * stride;
+    NSASM_TRY(device_alloc(&m->patch_rec, n, "patch records"));
+    const bool gather = m->scatter == NSASM_SCATTER_PATCH_GATHER;
+    if (gather) NSASM_TRY(device_alloc(&m->patch_ref, n, "patch partial positions"));
+    NSASM_TRY(device_alloc(&m->elem_loc, static_cast<size_t>(m->n_elems), "element LDS positions"));
+    uint8_t *position = nullptr;
+    NSASM_TRY(device_alloc(&position, static_cast<size_t>(m->patch_node_refs), "patch node positions"));
+    const uint32_t *off = reinterpret_cast<const uint32_t *>(m->patch_off);
+    k_patch_color<<<static_cast<unsigned>(m->n_patches), kThreads, 0, stream>>>(
+        off, m->patch_node_start, m->elem_pos, m->n_elems, m->patch_elems, position, m->elem_loc);
+    nsasm_status st = check_launch("k_patch_color");
+    if (st == NSASM_OK) {
+        k_patch_pad<<<static_cast<unsigned>(m->n_patches), kThreads, 0, stream>>>(
+            off, m->patch_nodes, m->patch_node_start, position, gather ? m->ref_slot : nullptr, m->n_elems,
+            m->patch_elems, stride, m->patch_rec, m->patch_ref);
+        st = check_launch("k_patch_pad");
+    }
+    if (st == NSASM_OK) {
+        hipError_t err = hipStreamSynchronize(stream);
+        if (err != hipSuccess) st = hip_fail(err, "patch records");
+    }
+    device_free(position);
+    NSASM_TRY(st);
+    m->patch_stride = stride;
+    free_compact_patches(m);
+    return NSASM_OK;
+}
+
 nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64_t ne,
                     const nsasm_mesh_options &opt, hipStream_t stream, nsasm_mesh *m) {
     m->n_nodes = nn;
@@ -538,6 +712,7 @@ nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64
         if (st == NSASM_OK) {
             m->scatter = (opt.scatter == NSASM_SCATTER_PATCH) ? NSASM_SCATTER_PATCH : NSASM_SCATTER_PATCH_GATHER;
             if (m->scatter == NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(build_node_gather(m, stream));
+            NSASM_TRY(build_patch_records(m, stream));
         } else if (!(st == NSASM_ERR_UNSUPPORTED && opt.scatter == NSASM_SCATTER_AUTO)) {
             return st;
         }
