@@ -466,6 +466,28 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
     });
 }
 
+// acc = sum of the slots [beg, end) of every component, in a fixed order:
+// chunks of four whose loads are independent (the run is read in parallel,
+// not one LDS round trip per slot); indices past the run are clamped to its
+// first slot and the values masked, so every read stays inside the run.
+template <typename T, int NOUT, int KS>
+__device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[NOUT]) {
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
+    for (int k = beg; k < end; k += 4) {
+        T v[4][NOUT];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = k + j < end;
+            const int kk = in ? k + j : beg;
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) v[j][i] = in ? sval[i][kk] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < NOUT; ++i) acc[i] += (v[0][i] + v[1][i]) + (v[2][i] + v[3][i]);
+    }
+}
+
 // One workgroup per patch (see the file header).  LDS holds the patch's
 // node data while elements gather it, then (reusing the same bytes) the
 // element contributions at their precomputed slots: slots are sorted by node,
@@ -559,11 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     __syncthreads();
     if (has_node) {
         T acc[FL::NOUT];
-#pragma unroll
-        for (int i = 0; i < FL::NOUT; ++i) acc[i] = T(0);
-        for (int k = s_beg; k < s_end; ++k)
-#pragma unroll
-            for (int i = 0; i < FL::NOUT; ++i) acc[i] += sval[i][k];
+        run_sum<T, FL::NOUT, kS>(sval, s_beg, s_end, acc);
         if (GATHER) {
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) out[FL::NOUT * static_cast<int64_t>(slot) + i] = acc[i];
@@ -571,6 +589,27 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) global_add(&out[FL::NOUT * node + i], acc[i]);
         }
+    }
+}
+
+// acc = sum of the partial sums [kb, ke), in a fixed order: pairs whose loads
+// are independent; an index past the run is clamped to its first entry (the
+// loop body runs only when the run is not empty) and the value masked.
+template <typename T, int NOUT>
+__device__ inline void gather_sum(const T *__restrict__ partial, int64_t kb, int64_t ke, T (&acc)[NOUT]) {
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
+    for (int64_t k = kb; k < ke; k += 2) {
+        const bool in = k + 1 < ke;
+        const int64_t k1 = in ? k + 1 : kb;
+        T v0[NOUT], v1[NOUT];
+#pragma unroll
+        for (int i = 0; i < NOUT; ++i) {
+            v0[i] = partial[NOUT * k + i];
+            v1[i] = partial[NOUT * k1 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < NOUT; ++i) acc[i] += v0[i] + (in ? v1[i] : T(0));
     }
 }
 
@@ -583,12 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_partials(int64_t nn, const 
     const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
     if (n >= nn) return;
     T acc[NOUT];
-#pragma unroll
-    for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
-    const int64_t kb = ref_off[n], ke = ref_off[n + 1];
-    for (int64_t k = kb; k < ke; ++k)
-#pragma unroll
-        for (int i = 0; i < NOUT; ++i) acc[i] += partial[NOUT * k + i];
+    gather_sum<T, NOUT>(partial, ref_off[n], ref_off[n + 1], acc);
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) out[NOUT * n + i] = accumulate ? out[NOUT * n + i] + acc[i] : acc[i];
 }
@@ -607,11 +641,8 @@ __global__ __launch_bounds__(kThreads) void k_gather_update(int64_t nn, const in
                                                             T *__restrict__ rhs, T *u_new) {
     const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
     if (n >= nn) return;
-    T acc[3] = {T(0), T(0), T(0)};
-    const int64_t kb = ref_off[n], ke = ref_off[n + 1];
-    for (int64_t k = kb; k < ke; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) acc[i] += partial[3 * k + i];
+    T acc[3];
+    gather_sum<T, 3>(partial, ref_off[n], ref_off[n + 1], acc);
     if (rhs) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) rhs[3 * n + i] = acc[i];
