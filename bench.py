@@ -246,24 +246,25 @@ def main():
                                  ("rotational", wl.cs, "smagorinsky", "rotational"),
                                  ("emac", wl.cs, "smagorinsky", "emac")):
         vp = api.Params(wl.rho, wl.mu, cs, wl.body_force, model, conv)
-        tf = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, vp, out=scratch, accumulate=acc), args.kernel_reps)[0]
+        # medians: one slow launch must not stand for the variant
+        tf = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, vp, out=scratch, accumulate=acc), args.kernel_reps)[1]
         tv = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, vp, out=scratch, accumulate=acc),
-                       args.kernel_reps)[0]
+                       args.kernel_reps)[1]
         variants[tag] = {"eddy_model": model, "smagorinsky_cs": cs, "convective_form": conv, "fwd_ms": tf,
                          "vjp_ms": tv, "fwd_vjp_elems_per_s": ne / ((tf + tv) * 1e-3)}
     tj = kernel_ms(lambda: api.assemble_rhs_jvp(mesh, u, du, dpr, prm, out=scratch, accumulate=acc),
-                   args.kernel_reps)[0]
-    tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[0]
+                   args.kernel_reps)[1]
+    tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[1]
     variants["jvp"] = {"ms": tj, "elems_per_s": ne / (tj * 1e-3)}
     variants["vjp_p"] = {"ms": tp, "elems_per_s": ne / (tp * 1e-3)}
     # explicit momentum stage u + dt R / (rho V^L) with a boundary Dirichlet
     # mask; with the gather scatter the update is fused into the gather kernel
     bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
     mask = mesh.to_mesh_order(to_dev(np.where(bnd, 7.0, 0.0), torch.float64)).to(torch.uint8)
-    tu = kernel_ms(lambda: api.explicit_update(mesh, u, p, prm, 1e-3, mask, out=scratch), args.kernel_reps)[0]
+    tu = kernel_ms(lambda: api.explicit_update(mesh, u, p, prm, 1e-3, mask, out=scratch), args.kernel_reps)[1]
     variants["explicit_update"] = {"ms": tu, "elems_per_s": ne / (tu * 1e-3),
                                    "fused": mesh.info["scatter"] == "patch_gather",
-                                   "vs_forward_ms": tu - kernels["fwd"]["mean_ms"]}
+                                   "vs_forward_ms": tu - kernels["fwd"]["median_ms"]}
     log("[bench] variants (fwd+vjp G elem/s): " + ", ".join(
         f"{k} {v['fwd_vjp_elems_per_s'] / 1e9:.2f}" for k, v in variants.items() if "fwd_vjp_elems_per_s" in v)
         + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us")

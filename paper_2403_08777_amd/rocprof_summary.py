@@ -82,10 +82,16 @@ def traffic(args):
     fs, fkib = copy_scale(f_rows, "FETCH_SIZE")
     ws, wkib = copy_scale(w_rows, "WRITE_SIZE")
     calls = {}
+
+    def targs(name):
+        m = re.match(r"(\w+)<(.*)>$", name)
+        return (m.group(1), [a.strip() for a in m.group(2).split(",")]) if m else (name, [])
+
+    # the benchmark's calls: k_assemble_patch<double, EDDY none, CONV advective,
+    # MODE, GATHER> followed by k_gather_partials<double, 3>
     for mode, tag in (("fwd", "0"), ("vjp", "1")):
-        parts = [key for key in fetch if key[0].startswith("k_assemble_patch<double") and
-                 key[0].split(",")[2].strip() == tag]
-        gathers = [key for key in fetch if key[0] == "k_gather_partials<double>"]
+        parts = [key for key in fetch if targs(key[0]) == ("k_assemble_patch", ["double", "0", "0", tag, "true"])]
+        gathers = [key for key in fetch if targs(key[0]) == ("k_gather_partials", ["double", "3"])]
         keys = parts + gathers
         if not parts:
             continue
