@@ -240,9 +240,8 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
 template <typename T, int EDDY, int CONV, typename Sink>
 __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
                                    const KParams<T> &P, Sink &&emit) {
-    T G[3][3], Lam[3][3];
+    T G[3][3];
     vector_gradient(gN, ue, G);
-    vector_gradient(gN, le, Lam);
     const T sc = P.rho * vol * T(0.05);
     T U[3], L[3];
 #pragma unroll
@@ -253,46 +252,50 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
     T D[3][3];
     const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
     const T sv = mu_e * vol;
-    T se = T(0);  // V * (Lambda : G): weight of d mu_t / d G
-    if (EDDY != kNoEddy) {
-        T phi = T(0);
+    // M = sum_a lambda_a (x) y_a with y_a = (rho V / 20)(u_a + U) + mu_e V grad N_a
+    // (the forward's y_a): the convective part (rho V / 20)(P + L (x) U) and the
+    // viscous part mu_e V Lambda in one accumulation.  W = sum_a lambda_a (x) z_a,
+    // z_a = (rho V / 20)(u_a + U), is the convective part alone, which a general
+    // form K = G + conv_a tr(G) I + conv_b G^T turns into
+    // W + conv_a tr(W) I + conv_b W^T.  Phi = Lambda : G = sum_a lambda_a . G grad N_a
+    // weighs d mu_t / d G.
+    T M[3][3] = {}, W[3][3] = {}, phi = T(0);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 4; ++a) {
+        T z[3], y[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) phi += Lam[i][j] * G[i][j];
-        se = vol * phi;
-    }
-    // W = (rho V / 20)(P + L (x) U) is the convective part of M; a general
-    // form K = G + conv_a tr(G) I + conv_b G^T turns K : W into
-    // G : (W + conv_a tr(W) I + conv_b W^T).
-    T M[3][3];
-    if (CONV == kGeneral) {
-        T W[3][3];
+        for (int j = 0; j < 3; ++j) {
+            z[j] = sc * (ue[a][j] + U[j]);
+            y[j] = z[j] + sv * gN[a][j];
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
-                W[k][j] = sc * (pkj + L[k] * U[j]);
+                M[k][j] += le[a][k] * y[j];
+                if (CONV == kGeneral) W[k][j] += le[a][k] * z[j];
             }
+        if (EDDY != kNoEddy) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                phi += le[a][i] * (G[i][0] * gN[a][0] + G[i][1] * gN[a][1] + G[i][2] * gN[a][2]);
+        }
+    }
+    if (CONV == kGeneral) {
         const T atw = P.conv_a * (W[0][0] + W[1][1] + W[2][2]);
 #pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) M[k][j] += P.conv_b * W[j][k];
+            M[k][k] += atw;
+        }
+    }
+    if (EDDY != kNoEddy) {
+        const T se = vol * phi;
+#pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                M[k][j] = W[k][j] + P.conv_b * W[j][k] + sv * Lam[k][j];
-                if (k == j) M[k][j] += atw;
-                if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
-            }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const T pkj = le[0][k] * ue[0][j] + le[1][k] * ue[1][j] + le[2][k] * ue[2][j] + le[3][k] * ue[3][j];
-                M[k][j] = sc * (pkj + L[k] * U[j]) + sv * Lam[k][j];
-                if (EDDY != kNoEddy) M[k][j] += se * D[k][j];
-            }
+            for (int j = 0; j < 3; ++j) M[k][j] += se * D[k][j];
     }
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
 #pragma unroll
