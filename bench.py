@@ -30,7 +30,7 @@ FP64_PEAK_TFS = 78.6           # MI355X FP64 vector: 256 CUs x 2.4 GHz x 128 flo
 # gradient 54, pressure gradient 18 (forward) or adjoint gradient 54 (VJP),
 # element terms, plus 12 additions of the scatter-add.  Smagorinsky adds the
 # strain norm, filter width and (VJP) its derivative.
-FLOPS_PER_ELEMENT = {("fwd", False): 281, ("fwd", True): 317, ("vjp", False): 463, ("vjp", True): 538}
+FLOPS_PER_ELEMENT = {("fwd", False): 281, ("fwd", True): 317, ("vjp", False): 421, ("vjp", True): 578}
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 

@@ -24,9 +24,9 @@
 //   VJP, g = (dR/du)^T lambda, per element with L = sum_a lambda_a,
 //   P = sum_a lambda_a (x) u_a, Lambda = sum_a lambda_a (x) grad N_a:
 //     g_b = -M grad N_b - (rho V / 20) G^T (lambda_b + L),
-//     M = (rho V / 20)(P + L (x) U) + mu_e V Lambda + V Phi kappa S,
-//   where Phi = Lambda : G and kappa = rho (cs Delta)^2 2 / |S| (0 if |S| = 0)
-//   is the derivative of the Smagorinsky viscosity.
+//     M = (rho V / 20)(P + L (x) U) + mu_e V Lambda + V Phi D = sum_a lambda_a (x) y_a + V Phi D,
+//   where Phi = Lambda : G = sum_a lambda_a . G grad N_a and D = d mu_t / d G
+//   (for Smagorinsky rho (cs Delta)^2 2 S / |S|, 0 if |S| = 0).
 //
 // Scatter strategies:
 //   ATOMIC: one thread per element, 12 global atomic adds.
