@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--scatter", default="auto", choices=["auto", "atomic", "patch"])
     ap.add_argument("--patch-elems", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 1 GiB (HBM bandwidth and counter calibration)")
     return ap.parse_args()
@@ -167,6 +168,36 @@ def main():
     value = ne / (ms_per_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.4f} ms/step (wall {wall_ms / args.steps:.4f}), "
         f"{value / 1e9:.2f} G elem/s fwd+VJP")
+
+    # the same step captured once in a HIP graph and replayed K times (no
+    # host launch overhead between the four kernels); the replay must
+    # reproduce the eager outputs bit for bit (gather scatter: fixed order)
+    graph = None
+    if not args.no_graph:
+        ref_rhs, ref_grad = rhs.clone(), grad.clone()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(rhs, ref_rhs) and torch.equal(grad, ref_grad))
+        start.record()
+        for _ in range(args.steps):
+            g.replay()
+        stop.record()
+        torch.cuda.synchronize()
+        g_ms = start.elapsed_time(stop) / args.steps
+        graph = {"ms_per_step": g_ms, "elems_per_s": ne / (g_ms * 1e-3), "bitwise_equal_to_eager": same}
+        log(f"[bench] HIP graph replay: {g_ms:.4f} ms/step, {ne / (g_ms * 1e-3) / 1e9:.2f} G elem/s "
+            f"(bitwise equal to eager: {same})")
+        del g
 
     # per-call durations of the assembly kernels alone, HIP events on the
     # launch stream; with atomic scatter, ACCUMULATE skips the zero-fill
@@ -294,6 +325,7 @@ def main():
         "kernels": kernels,
         "forms": forms,
         "variants": variants,
+        "graph_replay": graph,
         "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms},
     }
 
