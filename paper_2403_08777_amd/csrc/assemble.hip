@@ -491,13 +491,16 @@ __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[N
     }
 }
 
-// One workgroup per patch (see the file header).  LDS holds the patch's
-// node data while elements gather it, then (reusing the same bytes) the
-// element contributions at their precomputed slots: slots are sorted by node,
-// so each node's contributions form one contiguous run that a single thread
+// One workgroup per patch (see the file header).  Thread t loads patch
+// record t (node id, slot run, LDS position; records are padded to a fixed
+// stride) and stages the node's coordinates and fields at that position;
+// element t reads its vertices at the positions elem_loc gives (chosen at
+// mesh creation to spread LDS banks).  Then, reusing the same bytes, the
+// element contributions go to their precomputed slots: slots are sorted by
+// node, so each node's contributions form one contiguous run that one thread
 // sums in a fixed order.  GATHER = false adds each node sum to `out` with a
 // global atomic; GATHER = true stores it to the node-major partial-sum buffer
-// (position ref_slot of the patch reference), for k_gather_partials.
+// (position patch_ref of the record), for k_gather_partials.
 template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, int32_t stride, const int2 *__restrict__ patch_rec,
