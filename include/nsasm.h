@@ -36,8 +36,10 @@
  *    pointer.  A mesh owns its internal device buffers until destroyed.
  *  - No call throws or aborts; each returns an nsasm_status and, when it is
  *    not NSASM_OK, sets a thread-local message read by nsasm_last_error().
- *  - A mesh is immutable after creation: concurrent assembly calls on one mesh
- *    are safe when their output buffers differ.
+ *  - A mesh's description is immutable after creation.  With the atomic and
+ *    patch scatters, concurrent assembly calls on one mesh are safe when their
+ *    output buffers differ; with the gather scatter they share the mesh's
+ *    partial-sum buffer and must not overlap in time.
  */
 #ifndef NSASM_H
 #define NSASM_H
@@ -200,10 +202,16 @@ nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_
  * u   : device, n_nodes x 3, mesh order.    p : device, n_nodes, mesh order.
  * rhs : device, n_nodes x 3, mesh order; overwritten (or added to with
  *       NSASM_ACCUMULATE).  Must not overlap u or p.
- * Summation order across elements is unspecified (atomic adds), so results
- * may differ between calls by rounding.  Asynchronous on stream.
+ * With NSASM_SCATTER_PATCH_GATHER (the default where the mesh allows it) the
+ * summation order is fixed and results are bitwise reproducible; with the
+ * atomic scatters it is unspecified and results may differ between calls by
+ * rounding.  Calls on one gather-scatter mesh share its partial-sum buffer:
+ * they must not overlap in time (one stream, or ordered by events).  No
+ * allocation, memset or host synchronisation happens inside, so the call may
+ * be captured in a HIP graph.  Asynchronous on stream.
  * Errors: INVALID_ARGUMENT (null/host pointers, rho <= 0, mu < 0, cs < 0,
- * non-finite parameters, unknown precision, flags or eddy model), DEVICE.
+ * non-finite parameters, unknown precision, flags, eddy model or convective
+ * form, non-zero reserved field), DEVICE.
  */
 nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *params,
                                 nsasm_precision precision, const void *u, const void *p, void *rhs,
