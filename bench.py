@@ -288,6 +288,17 @@ def main():
     tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[1]
     variants["jvp"] = {"ms": tj, "elems_per_s": ne / (tj * 1e-3)}
     variants["vjp_p"] = {"ms": tp, "elems_per_s": ne / (tp * 1e-3)}
+
+    # the same forward + VJP through torch.autograd (NSAssembleRHS): output
+    # allocation and autograd bookkeeping included
+    u_req = u.detach().clone().requires_grad_(True)
+
+    def autograd_step():
+        u_req.grad = None
+        api.NSAssembleRHS.apply(u_req, p, mesh, prm).backward(lam)
+
+    ta = kernel_ms(autograd_step, args.kernel_reps)[1]
+    variants["autograd_fwd_bwd"] = {"ms": ta, "elems_per_s": ne / (ta * 1e-3)}
     # explicit momentum stage u + dt R / (rho V^L) with a boundary Dirichlet
     # mask; with the gather scatter the update is fused into the gather kernel
     bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
@@ -298,7 +309,8 @@ def main():
                                    "vs_forward_ms": tu - kernels["fwd"]["median_ms"]}
     log("[bench] variants (fwd+vjp G elem/s): " + ", ".join(
         f"{k} {v['fwd_vjp_elems_per_s'] / 1e9:.2f}" for k, v in variants.items() if "fwd_vjp_elems_per_s" in v)
-        + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us")
+        + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us, "
+        f"autograd forward + backward {ta * 1e3:.1f} us")
 
     result = {
         "metric": "elements/s (FP64 forward + velocity VJP assembly)",
@@ -326,7 +338,8 @@ def main():
         "forms": forms,
         "variants": variants,
         "graph_replay": graph,
-        "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms},
+        "setup": {"mesh_create_ms": create_ms, "to_mesh_order_ms_per_vector_field": reorder_ms,
+                  "device": torch.cuda.get_device_name(dev), "hip": getattr(torch.version, "hip", None)},
     }
 
     if args.copy_calibration:
