@@ -135,7 +135,9 @@ typedef struct {
     int32_t renumber;    /* 1 (default): sort elements along a Morton curve and
                             renumber nodes by first touch; 0: keep user order */
     int32_t scatter;     /* nsasm_scatter */
-    int32_t patch_elems; /* elements per patch, 32..256 in steps of 32 (0 = 256) */
+    int32_t patch_elems; /* elements per patch, 32..256 in steps of 32; 0 = 256,
+                            or 128 when a 256-element patch would touch more
+                            than 256 distinct nodes */
     int32_t reserved;    /* must be 0 */
 } nsasm_mesh_options;
 

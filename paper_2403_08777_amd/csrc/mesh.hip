@@ -707,8 +707,14 @@ nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64
 
     m->scatter = NSASM_SCATTER_ATOMIC;
     if (opt.scatter != NSASM_SCATTER_ATOMIC) {
-        const int elems = opt.patch_elems > 0 ? opt.patch_elems : kMaxPatchElems;
+        // default size: kMaxPatchElems, halved once if a patch touches too many
+        // nodes (a mesh without locality fits neither and keeps atomic scatter)
+        int elems = opt.patch_elems > 0 ? opt.patch_elems : kMaxPatchElems;
         nsasm_status st = build_patches(m, elems, stream);
+        if (st == NSASM_ERR_UNSUPPORTED && opt.patch_elems == 0) {
+            elems /= 2;
+            st = build_patches(m, elems, stream);
+        }
         if (st == NSASM_OK) {
             m->scatter = (opt.scatter == NSASM_SCATTER_PATCH) ? NSASM_SCATTER_PATCH : NSASM_SCATTER_PATCH_GATHER;
             if (m->scatter == NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(build_node_gather(m, stream));

@@ -261,3 +261,37 @@ def test_anisotropic_elements_vreman():
     e_gpu, e_ora = oracle.rel_l2(got, ref), oracle.rel_l2(ora, ref)
     log(f"anisotropic vreman vs high precision: kernel {e_gpu:.2e}, oracle {e_ora:.2e}")
     assert e_gpu <= max(1e-13, 10 * e_ora)
+
+
+def test_auto_halves_patches_for_a_tet_strip():
+    """A strip of tetrahedra on a helix, tet k = (k, k+1, k+2, k+3): 256
+    consecutive tets touch 259 nodes, 128 touch 131.  The default options
+    must fall back to 128-element patches (not to atomic scatter) and keep
+    FP64 parity."""
+    from paper_2403_08777_amd import api, synth
+
+    nt = 1000
+    k = np.arange(nt + 3)
+    ang = 2 * np.pi * k / 3.3
+    coords = np.stack([0.05 * k, np.cos(ang), np.sin(ang)], axis=1)
+    conn = np.stack([k[:nt], k[:nt] + 1, k[:nt] + 2, k[:nt] + 3], axis=1).astype(np.int32)
+    vol, _ = oracle.geometry(coords, conn)
+    assert vol.min() > 1e-3
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((nt + 3, 3))
+    p = rng.standard_normal(nt + 3)
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev))
+    info = mesh.info
+    log(f"tet strip: {info}")
+    assert info["scatter"] == "patch_gather" and info["patch_elems"] == 128
+    assert info["max_patch_nodes"] <= 256
+    prm = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    got = mesh.from_mesh_order(api.assemble_rhs(mesh, tm(u), tm(p), prm)).cpu().numpy()
+    ref = oracle.rhs(coords, conn, u, p, oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE))
+    assert oracle.rel_l2(got, ref) <= TOL64
+    # an explicit 256-element request cannot be served with patches
+    with pytest.raises(api.NsasmError):
+        api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev), scatter="patch_gather",
+                 patch_elems=256)
