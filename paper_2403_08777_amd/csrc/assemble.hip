@@ -218,8 +218,19 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
         b[i] = w4 * (P.rho_f[i] - q[i]);
     }
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
+    // Vertices 1..3 directly; vertex 0 from the element sum
+    //   sum_a R^e_a = 4 b - 5 (rho V / 20) K U   (sum_a grad N_a = 0,
+    //   sum_a (u_a + U) = 5 U), K = G (+ conv_a tr(G) I + conv_b G^T),
+    // so that neither u_0 nor grad N_0 is needed after G and U.
+    T rsum[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int i = 0; i < 3; ++i) {
+        rsum[i] = T(4) * b[i] - T(5) * sc * (G[i][0] * U[0] + G[i][1] * U[1] + G[i][2] * U[2]);
+        if (CONV == kGeneral)
+            rsum[i] -= T(5) * sc * (at * U[i] + P.conv_b * (G[0][i] * U[0] + G[1][i] * U[1] + G[2][i] * U[2]));
+    }
+#pragma unroll
+    for (int a = 1; a < 4; ++a) {
         T z[3], y[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -232,9 +243,11 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
             re[i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
             if (CONV == kGeneral)
                 re[i] -= at * z[i] + P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
+            rsum[i] -= re[i];
         }
         emit(a, re);
     }
+    emit(0, rsum);
 }
 
 template <typename T, int EDDY, int CONV, typename Sink>
