@@ -40,6 +40,7 @@
 //           atomics anywhere, bitwise reproducible, no zero-fill.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -250,18 +251,29 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
     emit(0, rsum);
 }
 
-template <typename T, int EDDY, int CONV, typename Sink>
-__device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&le)[4][3],
-                                   const KParams<T> &P, Sink &&emit) {
-    T G[3][3];
-    vector_gradient(gN, ue, G);
-    const T sc = P.rho * vol * T(0.05);
-    T U[3], L[3];
+// ldu(a, i) and ldl(a, i) return u_a[i] and lambda_a[i].  Each is called
+// where its value is used: u_a for G and U and again in the accumulation of M,
+// lambda_a there and again in the per-vertex terms, so a caller that reads
+// them from LDS keeps one vertex's values live instead of all four; the
+// compiler barriers keep the second reads from being merged with the first.
+// Vertex 0 comes from the element sum  sum_b g_b = -5 (rho V / 20) K^T L
+// (sum_b grad N_b = 0, sum_b (lambda_b + L) = 5 L).
+template <typename T, int EDDY, int CONV, typename LdU, typename LdL, typename Sink>
+__device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&ldl, const KParams<T> &P,
+                                   Sink &&emit) {
+    T G[3][3], U[3];
+    {
+        T ue[4][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
-        L[i] = le[0][i] + le[1][i] + le[2][i] + le[3][i];
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ue[a][i] = ldu(a, i);
+        vector_gradient(gN, ue, G);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
     }
+    asm volatile("" ::: "memory");
+    const T sc = P.rho * vol * T(0.05);
     T D[3][3];
     const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
     const T sv = mu_e * vol;
@@ -272,28 +284,31 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
     // form K = G + conv_a tr(G) I + conv_b G^T turns into
     // W + conv_a tr(W) I + conv_b W^T.  Phi = Lambda : G = sum_a lambda_a . G grad N_a
     // weighs d mu_t / d G.
-    T M[3][3] = {}, W[3][3] = {}, phi = T(0);
+    T M[3][3] = {}, W[3][3] = {}, phi = T(0), L[3] = {};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        T z[3], y[3];
+        T la[3], z[3], y[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            z[j] = sc * (ue[a][j] + U[j]);
+            la[j] = ldl(a, j);
+            L[j] += la[j];
+            z[j] = sc * (ldu(a, j) + U[j]);
             y[j] = z[j] + sv * gN[a][j];
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                M[k][j] += le[a][k] * y[j];
-                if (CONV == kGeneral) W[k][j] += le[a][k] * z[j];
+                M[k][j] += la[k] * y[j];
+                if (CONV == kGeneral) W[k][j] += la[k] * z[j];
             }
         if (EDDY != kNoEddy) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                phi += le[a][i] * (G[i][0] * gN[a][0] + G[i][1] * gN[a][1] + G[i][2] * gN[a][2]);
+                phi += la[i] * (G[i][0] * gN[a][0] + G[i][1] * gN[a][1] + G[i][2] * gN[a][2]);
         }
     }
+    asm volatile("" ::: "memory");
     if (CONV == kGeneral) {
         const T atw = P.conv_a * (W[0][0] + W[1][1] + W[2][2]);
 #pragma unroll
@@ -311,22 +326,32 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, const T (&ue)[4][
             for (int j = 0; j < 3; ++j) M[k][j] += se * D[k][j];
     }
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const T w0 = le[b][0] + L[0], w1 = le[b][1] + L[1], w2 = le[b][2] + L[2];
-        T ge[3];
+    // (K^T w)_k = (G^T w)_k + conv_a tr(G) w_k + conv_b (G w)_k
+    auto kt = [&](const T (&w)[3], T (&kw)[3]) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            // (K^T w)_k = (G^T w)_k + conv_a tr(G) w_k + conv_b (G w)_k
-            T kw = G[0][k] * w0 + G[1][k] * w1 + G[2][k] * w2;
-            if (CONV == kGeneral) {
-                const T wk = (k == 0) ? w0 : (k == 1) ? w1 : w2;
-                kw += at * wk + P.conv_b * (G[k][0] * w0 + G[k][1] * w1 + G[k][2] * w2);
-            }
-            ge[k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw;
+            kw[k] = G[0][k] * w[0] + G[1][k] * w[1] + G[2][k] * w[2];
+            if (CONV == kGeneral) kw[k] += at * w[k] + P.conv_b * (G[k][0] * w[0] + G[k][1] * w[1] + G[k][2] * w[2]);
+        }
+    };
+    T gsum[3];
+    kt(L, gsum);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gsum[k] *= -T(5) * sc;
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+        T w[3], kw[3], ge[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) w[j] = ldl(b, j) + L[j];
+        kt(w, kw);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ge[k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw[k];
+            gsum[k] -= ge[k];
         }
         emit(b, ge);
     }
+    emit(0, gsum);
 }
 
 // Pressure VJP: the pressure term -(V/4) q at every vertex is linear in p,
@@ -412,7 +437,9 @@ template <typename T, int EDDY, int CONV, int MODE, typename Sink>
 __device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3], const T (&eb)[4][3],
                                   const T (&ec)[4], const KParams<T> &P, Sink &&emit) {
     if constexpr (MODE == kForward) element_rhs<T, EDDY, CONV>(gN, vol, ea, ec, P, emit);
-    if constexpr (MODE == kVjp) element_vjp<T, EDDY, CONV>(gN, vol, ea, eb, P, emit);
+    if constexpr (MODE == kVjp)
+        element_vjp<T, EDDY, CONV>(
+            gN, vol, [&](int a, int i) { return ea[a][i]; }, [&](int a, int i) { return eb[a][i]; }, P, emit);
     if constexpr (MODE == kVjpP) element_vjp_p(gN, vol, eb, emit);
     if constexpr (MODE == kJvp) element_jvp<T, EDDY, CONV>(gN, vol, ea, eb, ec, P, emit);
     if constexpr (MODE == kMass) {
@@ -525,6 +552,11 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
     constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
+    // The FP64 VJP reads u_a and lambda_a from LDS where it uses them (twice
+    // each) instead of holding all four vertices in registers: 95 instead of
+    // 108 VGPRs, five waves per SIMD instead of four.  In FP32 the kernel
+    // already runs eight waves and the extra LDS reads would only cost.
+    constexpr bool kLdsVjp = MODE == kVjp && std::is_same<T, double>::value;
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
@@ -551,7 +583,6 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
         s_beg = rec.y & 0x7ff;
         s_end = (rec.y >> 11) & 0x7ff;
         lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);
-        if (GATHER) slot = patch_ref[patch * stride + t];
     }
     const bool has_node = node >= 0;
     if (has_node) {
@@ -576,8 +607,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 xe[a][i] = sx[i][la[a]];
-                if (FL::NA) ea[a][i] = sf[i][la[a]];
-                if (FL::NB) eb[a][i] = sf[FL::NA + i][la[a]];
+                if (FL::NA && !kLdsVjp) ea[a][i] = sf[i][la[a]];
+                if (FL::NB && !kLdsVjp) eb[a][i] = sf[FL::NA + i][la[a]];
             }
             if (FL::NC) ec[a] = sf[FL::NA + FL::NB][la[a]];
         }
@@ -585,10 +616,16 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
         tet_geometry(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
-        element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, [&](int a, const T (&v)[3]) {
+        auto sink = [&](int a, const T (&v)[3]) {
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) r[a][i] = v[i];
-        });
+        };
+        if constexpr (kLdsVjp)
+            element_vjp<T, EDDY, CONV>(
+                gN, vol, [&](int a, int i) { return sf[i][la[a]]; }, [&](int a, int i) { return sf[3 + i][la[a]]; },
+                P, sink);
+        else
+            element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, sink);
     }
     __syncthreads();  // node data is dead from here on; its bytes become slots
     if (t < nel) {
@@ -598,6 +635,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
             for (int i = 0; i < FL::NOUT; ++i) sval[i][sl[a]] = r[a][i];
     }
     __syncthreads();
+    if (GATHER && has_node) slot = patch_ref[patch * stride + t];  // loaded late: fewer live registers
     if (has_node) {
         T acc[FL::NOUT];
         run_sum<T, FL::NOUT, kS>(sval, s_beg, s_end, acc);
