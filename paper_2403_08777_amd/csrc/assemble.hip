@@ -196,11 +196,23 @@ __device__ inline T eddy_viscosity(const T (&G)[3][3], T vol, T rho_c, T (&D)[3]
     return c * s;
 }
 
-template <typename T, int EDDY, int CONV, typename Sink>
-__device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][3], const T (&pe)[4],
-                                   const KParams<T> &P, Sink &&emit) {
-    T G[3][3];
-    vector_gradient(gN, ue, G);
+// ldu(a, i) returns u_a[i]; it is called for G and U and again where u_a
+// enters y_a (see element_vjp on why a caller may read it from LDS twice).
+template <typename T, int EDDY, int CONV, typename LdU, typename Sink>
+__device__ inline void element_rhs(const T (&gN)[4][3], T vol, LdU &&ldu, const T (&pe)[4], const KParams<T> &P,
+                                   Sink &&emit) {
+    T G[3][3], U[3];
+    {
+        T ue[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ue[a][i] = ldu(a, i);
+        vector_gradient(gN, ue, G);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
+    }
+    asm volatile("" ::: "memory");
     T q[3];
     {
         const T d1 = pe[1] - pe[0], d2 = pe[2] - pe[0], d3 = pe[3] - pe[0];
@@ -212,10 +224,9 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
     const T sc = P.rho * vol * T(0.05);
     const T sv = mu_e * vol;
     const T w4 = vol * T(0.25);
-    T U[3], b[3];
+    T b[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        U[i] = ue[0][i] + ue[1][i] + ue[2][i] + ue[3][i];
         b[i] = w4 * (P.rho_f[i] - q[i]);
     }
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
@@ -235,7 +246,7 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, const T (&ue)[4][
         T z[3], y[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            z[j] = sc * (ue[a][j] + U[j]);
+            z[j] = sc * (ldu(a, j) + U[j]);
             y[j] = z[j] + sv * gN[a][j];
         }
         T re[3];
@@ -436,7 +447,8 @@ __device__ inline void element_jvp(const T (&gN)[4][3], T vol, const T (&ue)[4][
 template <typename T, int EDDY, int CONV, int MODE, typename Sink>
 __device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3], const T (&eb)[4][3],
                                   const T (&ec)[4], const KParams<T> &P, Sink &&emit) {
-    if constexpr (MODE == kForward) element_rhs<T, EDDY, CONV>(gN, vol, ea, ec, P, emit);
+    if constexpr (MODE == kForward)
+        element_rhs<T, EDDY, CONV>(gN, vol, [&](int a, int i) { return ea[a][i]; }, ec, P, emit);
     if constexpr (MODE == kVjp)
         element_vjp<T, EDDY, CONV>(
             gN, vol, [&](int a, int i) { return ea[a][i]; }, [&](int a, int i) { return eb[a][i]; }, P, emit);
@@ -552,11 +564,12 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
     constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
-    // The FP64 VJP reads u_a and lambda_a from LDS where it uses them (twice
-    // each) instead of holding all four vertices in registers: 95 instead of
-    // 108 VGPRs, five waves per SIMD instead of four.  In FP32 the kernel
+    // The FP64 forward and VJP read u_a (and lambda_a) from LDS where they use
+    // them (twice each) instead of holding all four vertices in registers:
+    // 79 instead of 86 VGPRs (forward, six waves per SIMD instead of five) and
+    // 93 instead of 108 (VJP, five instead of four).  In FP32 the kernel
     // already runs eight waves and the extra LDS reads would only cost.
-    constexpr bool kLdsVjp = MODE == kVjp && std::is_same<T, double>::value;
+    constexpr bool kLds = (MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value;
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
@@ -580,8 +593,6 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     if (t < stride) {
         const int2 rec = patch_rec[patch * stride + t];
         node = rec.x;
-        s_beg = rec.y & 0x7ff;
-        s_end = (rec.y >> 11) & 0x7ff;
         lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);
     }
     const bool has_node = node >= 0;
@@ -607,8 +618,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 xe[a][i] = sx[i][la[a]];
-                if (FL::NA && !kLdsVjp) ea[a][i] = sf[i][la[a]];
-                if (FL::NB && !kLdsVjp) eb[a][i] = sf[FL::NA + i][la[a]];
+                if (FL::NA && !kLds) ea[a][i] = sf[i][la[a]];
+                if (FL::NB && !kLds) eb[a][i] = sf[FL::NA + i][la[a]];
             }
             if (FL::NC) ec[a] = sf[FL::NA + FL::NB][la[a]];
         }
@@ -620,10 +631,11 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) r[a][i] = v[i];
         };
-        if constexpr (kLdsVjp)
-            element_vjp<T, EDDY, CONV>(
-                gN, vol, [&](int a, int i) { return sf[i][la[a]]; }, [&](int a, int i) { return sf[3 + i][la[a]]; },
-                P, sink);
+        auto ldu = [&](int a, int i) { return sf[i][la[a]]; };
+        if constexpr (kLds && MODE == kForward)
+            element_rhs<T, EDDY, CONV>(gN, vol, ldu, ec, P, sink);
+        else if constexpr (kLds && MODE == kVjp)
+            element_vjp<T, EDDY, CONV>(gN, vol, ldu, [&](int a, int i) { return sf[3 + i][la[a]]; }, P, sink);
         else
             element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, sink);
     }
@@ -635,7 +647,14 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
             for (int i = 0; i < FL::NOUT; ++i) sval[i][sl[a]] = r[a][i];
     }
     __syncthreads();
-    if (GATHER && has_node) slot = patch_ref[patch * stride + t];  // loaded late: fewer live registers
+    // the slot run and the partial-sum position are loaded again (an L2 hit)
+    // rather than kept live through the element arithmetic
+    if (has_node) {
+        const int32_t ry = patch_rec[patch * stride + t].y;
+        s_beg = ry & 0x7ff;
+        s_end = (ry >> 11) & 0x7ff;
+        if (GATHER) slot = patch_ref[patch * stride + t];
+    }
     if (has_node) {
         T acc[FL::NOUT];
         run_sum<T, FL::NOUT, kS>(sval, s_beg, s_end, acc);
