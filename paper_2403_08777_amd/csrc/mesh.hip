@@ -404,26 +404,40 @@ __global__ __launch_bounds__(kThreads) void k_patch_color(const uint32_t *off, c
 // Fixed-stride patch records: entry t of patch p at p * stride + t, so an
 // assembly workgroup finds its nodes without first reading the patch offset.
 // rec.y packs the node's slot run [first, end) and its LDS position:
-// first | end << 11 | position << 22.
+// first | end << 11 | position << 22.  Records are ordered by decreasing run
+// length (ties by node): the assembly thread of record t sums that run, and a
+// wave loops as long as its longest run, so similar lengths share a wave.
 __global__ __launch_bounds__(kThreads) void k_patch_pad(const uint32_t *off, const int32_t *nodes,
                                                          const int32_t *start, const uint8_t *position,
                                                          const int32_t *ref_slot, int64_t ne, int elems,
                                                          int stride, int2 *rec, int32_t *ref) {
+    __shared__ int len[kMaxPatchNodes];
     const int64_t p = blockIdx.x;
     const int t = threadIdx.x;
-    if (t >= stride) return;
     const uint32_t beg = off[p], cnt = off[p + 1] - beg;
     const int nel = static_cast<int>(min<int64_t>(elems, ne - p * elems));
-    int2 r = make_int2(-1, 0);
-    int32_t s = 0;
-    if (static_cast<uint32_t>(t) < cnt) {
-        const int sb = start[beg + t];
-        const int se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
-        r = make_int2(nodes[beg + t], sb | (se << 11) | (static_cast<int>(position[beg + t]) << 22));
-        if (ref_slot) s = ref_slot[beg + t];
+    const bool real = static_cast<uint32_t>(t) < cnt;
+    int sb = 0, se = 0;
+    if (real) {
+        sb = start[beg + t];
+        se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
+        len[t] = se - sb;
     }
-    rec[p * stride + t] = r;
-    if (ref) ref[p * stride + t] = s;
+    __syncthreads();
+    if (real) {
+        const int mine = se - sb;
+        int slot = 0;  // this record's place: longer runs first, then node order
+        for (int u = 0; u < static_cast<int>(cnt); ++u) {
+            const int lu = len[u];
+            slot += (lu > mine || (lu == mine && u < t)) ? 1 : 0;
+        }
+        rec[p * stride + slot] =
+            make_int2(nodes[beg + t], sb | (se << 11) | (static_cast<int>(position[beg + t]) << 22));
+        if (ref) ref[p * stride + slot] = ref_slot ? ref_slot[beg + t] : 0;
+    } else if (t < stride) {
+        rec[p * stride + t] = make_int2(-1, 0);
+        if (ref) ref[p * stride + t] = 0;
+    }
 }
 
 // Number of patch references of every node (patch_nodes entries equal to it).
