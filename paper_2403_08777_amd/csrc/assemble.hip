@@ -230,6 +230,10 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, LdU &&ldu, const 
         b[i] = w4 * (P.rho_f[i] - q[i]);
     }
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
+    // z_a = (rho V / 20)(u_a + U) = sc u_a + sc U: one FMA per component.
+    T scU[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) scU[i] = sc * U[i];
     // Vertices 1..3 directly; vertex 0 from the element sum
     //   sum_a R^e_a = 4 b - 5 (rho V / 20) K U   (sum_a grad N_a = 0,
     //   sum_a (u_a + U) = 5 U), K = G (+ conv_a tr(G) I + conv_b G^T),
@@ -237,25 +241,32 @@ __device__ inline void element_rhs(const T (&gN)[4][3], T vol, LdU &&ldu, const 
     T rsum[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        rsum[i] = T(4) * b[i] - T(5) * sc * (G[i][0] * U[0] + G[i][1] * U[1] + G[i][2] * U[2]);
-        if (CONV == kGeneral)
-            rsum[i] -= T(5) * sc * (at * U[i] + P.conv_b * (G[0][i] * U[0] + G[1][i] * U[1] + G[2][i] * U[2]));
+        T ku = G[i][0] * scU[0] + G[i][1] * scU[1] + G[i][2] * scU[2];
+        if (CONV == kGeneral) ku += at * scU[i] + P.conv_b * (G[0][i] * scU[0] + G[1][i] * scU[1] + G[2][i] * scU[2]);
+        rsum[i] = T(4) * b[i] - T(5) * ku;
     }
 #pragma unroll
     for (int a = 1; a < 4; ++a) {
         T z[3], y[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            z[j] = sc * (ldu(a, j) + U[j]);
+            z[j] = sc * ldu(a, j) + scU[j];
             y[j] = z[j] + sv * gN[a][j];
         }
         T re[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            re[i] = b[i] - (G[i][0] * y[0] + G[i][1] * y[1] + G[i][2] * y[2]);
-            if (CONV == kGeneral)
-                re[i] -= at * z[i] + P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
-            rsum[i] -= re[i];
+            // b - G y as a chain of fused multiply-subtracts from b
+            T r = b[i];
+            r -= G[i][0] * y[0];
+            r -= G[i][1] * y[1];
+            r -= G[i][2] * y[2];
+            if (CONV == kGeneral) {
+                r -= at * z[i];
+                r -= P.conv_b * (G[0][i] * z[0] + G[1][i] * z[1] + G[2][i] * z[2]);
+            }
+            re[i] = r;
+            rsum[i] -= r;
         }
         emit(a, re);
     }
@@ -288,6 +299,9 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
     T D[3][3];
     const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
     const T sv = mu_e * vol;
+    T scU[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) scU[i] = sc * U[i];
     // M = sum_a lambda_a (x) y_a with y_a = (rho V / 20)(u_a + U) + mu_e V grad N_a
     // (the forward's y_a): the convective part (rho V / 20)(P + L (x) U) and the
     // viscous part mu_e V Lambda in one accumulation.  W = sum_a lambda_a (x) z_a,
@@ -303,7 +317,7 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
         for (int j = 0; j < 3; ++j) {
             la[j] = ldl(a, j);
             L[j] += la[j];
-            z[j] = sc * (ldu(a, j) + U[j]);
+            z[j] = sc * ldu(a, j) + scU[j];
             y[j] = z[j] + sv * gN[a][j];
         }
 #pragma unroll
@@ -345,20 +359,29 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
             if (CONV == kGeneral) kw[k] += at * w[k] + P.conv_b * (G[k][0] * w[0] + G[k][1] * w[1] + G[k][2] * w[2]);
         }
     };
-    T gsum[3];
-    kt(L, gsum);
+    // K^T (lambda_b + L) = K^T lambda_b + K^T L, and sum_b g_b = -5 (rho V / 20) K^T L
+    T c0[3], gsum[3];
+    kt(L, c0);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gsum[k] *= -T(5) * sc;
+    for (int k = 0; k < 3; ++k) {
+        c0[k] *= sc;
+        gsum[k] = T(-5) * c0[k];
+    }
 #pragma unroll
     for (int b = 1; b < 4; ++b) {
-        T w[3], kw[3], ge[3];
+        T lb[3], kw[3], ge[3];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) w[j] = ldl(b, j) + L[j];
-        kt(w, kw);
+        for (int j = 0; j < 3; ++j) lb[j] = ldl(b, j);
+        kt(lb, kw);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            ge[k] = -(M[k][0] * gN[b][0] + M[k][1] * gN[b][1] + M[k][2] * gN[b][2]) - sc * kw[k];
-            gsum[k] -= ge[k];
+            T g = -c0[k];
+            g -= sc * kw[k];
+            g -= M[k][0] * gN[b][0];
+            g -= M[k][1] * gN[b][1];
+            g -= M[k][2] * gN[b][2];
+            ge[k] = g;
+            gsum[k] -= g;
         }
         emit(b, ge);
     }
