@@ -3,6 +3,8 @@
     python -m paper_2403_08777_amd.rocprof_summary stats KERNEL_STATS_CSV --command CMD
     python -m paper_2403_08777_amd.rocprof_summary traffic --fetch F --write W \\
         --workload NAME --command-fetch CMD --command-write CMD
+    python -m paper_2403_08777_amd.rocprof_summary counters PMC_CSV --trace STATS_CSV \\
+        --command CMD --trace-command CMD
 
 ``stats`` prints a markdown table of per-kernel call counts and durations from
 a ``--kernel-trace --stats -f csv`` run.  ``traffic`` reads two ``--pmc`` runs
@@ -10,7 +12,10 @@ a ``--kernel-trace --stats -f csv`` run.  ``traffic`` reads two ``--pmc`` runs
 what it reads for the plain 1 GiB device copy that ``bench.py
 --copy-calibration`` performs, and prints a JSON record of the HBM bytes per
 assembly call (forward, VJP) tagged with a digest of the HIP sources, which
-``bench.py`` uses only while the kernels are unchanged.
+``bench.py`` uses only while the kernels are unchanged.  ``counters`` reads one
+``--pmc`` run of SQ instruction counters (and the kernel-trace statistics of
+the same workload for durations) and prints per-wave instruction counts and an
+estimate of how busy the vector ALUs were.
 """
 
 from __future__ import annotations
@@ -119,6 +124,40 @@ def stats(args):
               f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
 
 
+SIMDS = 256 * 4        # MI355X: 256 compute units, 4 SIMDs each
+CLOCK_HZ = 2.4e9       # peak engine clock
+VALU_CYCLES = 4        # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def counters(args):
+    rows = read_counters(args.pmc)
+    names = sorted({c for _, _, c, _ in rows})
+    med = {c: median_by_kernel(rows, c) for c in names}
+    dur = {}
+    with open(args.trace) as f:
+        for r in csv.DictReader(f):
+            dur[short_name(r["Name"])] = float(r["AverageNs"]) * 1e-9
+    pat = re.compile(args.kernels)
+    keys = sorted(k for k in med.get("SQ_WAVES", {}) if pat.search(k[0]))
+    shown = [c for c in names if c != "SQ_WAVES"]
+    print(f"Command: `{args.command}`\n")
+    print(f"Durations: `{args.trace_command}`\n")
+    print("Per-wave medians over the dispatches of each kernel (a wave is 64 elements in the element "
+          "phase). VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x average duration): "
+          "the share of SIMD cycles that issued vector instructions, assuming the peak clock.\n")
+    print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
+          " | avg us | VALU busy |")
+    print("|---|---:|---:|" + "---:|" * len(shown) + "---:|---:|")
+    for key in keys:
+        waves = med["SQ_WAVES"][key]
+        vals = " | ".join(f"{med[c].get(key, float('nan')) / waves:.1f}" for c in shown)
+        d = dur.get(key[0])
+        busy = (med["SQ_INSTS_VALU"][key] * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
+                if d and "SQ_INSTS_VALU" in med else float("nan"))
+        print(f"| `{key[0]}` | {key[1]} | {waves:.0f} | {vals} | "
+              f"{d * 1e6 if d else float('nan'):.1f} | {busy:.2f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -133,8 +172,14 @@ def main():
     t.add_argument("--scatter", default="patch_gather")
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("pmc")
+    c.add_argument("--trace", required=True, help="kernel_stats.csv of a --kernel-trace --stats run")
+    c.add_argument("--command", required=True)
+    c.add_argument("--trace-command", required=True)
+    c.add_argument("--kernels", default=r"k_assemble_patch<\w+, 0, 0, [01], true>|k_gather_partials")
     args = ap.parse_args()
-    (stats if args.cmd == "stats" else traffic)(args)
+    {"stats": stats, "traffic": traffic, "counters": counters}[args.cmd](args)
 
 
 if __name__ == "__main__":
