@@ -143,8 +143,10 @@ def counters(args):
     print(f"Command: `{args.command}`\n")
     print(f"Durations: `{args.trace_command}`\n")
     print("Per-wave medians over the dispatches of each kernel (a wave is 64 elements in the element "
-          "phase). VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x average duration): "
-          "the share of SIMD cycles that issued vector instructions, assuming the peak clock.\n")
+          "phase). VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x average duration), an "
+          "estimate of the share of SIMD cycles spent issuing vector instructions: 4 cycles is what a "
+          "wave64 FP64 FMA takes on a 16-lane SIMD (instructions that issue faster make it an "
+          "overestimate) and 2.4 GHz is the peak clock (a lower clock makes it an underestimate).\n")
     print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
           " | avg us | VALU busy |")
     print("|---|---:|---:|" + "---:|" * len(shown) + "---:|---:|")
