@@ -3,8 +3,8 @@
     python -m paper_2403_08777_amd.rocprof_summary stats KERNEL_STATS_CSV --command CMD
     python -m paper_2403_08777_amd.rocprof_summary traffic --fetch F --write W \\
         --workload NAME --command-fetch CMD --command-write CMD
-    python -m paper_2403_08777_amd.rocprof_summary counters PMC_CSV --trace STATS_CSV \\
-        --command CMD --trace-command CMD
+    python -m paper_2403_08777_amd.rocprof_summary counters PMC_CSV [PMC_CSV ...] --trace STATS_CSV \\
+        --command CMD --trace-command CMD [--json-out FILE]
 
 ``stats`` prints a markdown table of per-kernel call counts and durations from
 a ``--kernel-trace --stats -f csv`` run.  ``traffic`` reads two ``--pmc`` runs
@@ -130,7 +130,7 @@ VALU_CYCLES = 4        # a wave64 VALU instruction occupies a 16-lane SIMD for 4
 
 
 def counters(args):
-    rows = read_counters(args.pmc)
+    rows = [r for path in args.pmc for r in read_counters(path)]
     names = sorted({c for _, _, c, _ in rows})
     med = {c: median_by_kernel(rows, c) for c in names}
     dur = {}
@@ -140,24 +140,54 @@ def counters(args):
     pat = re.compile(args.kernels)
     keys = sorted(k for k in med.get("SQ_WAVES", {}) if pat.search(k[0]))
     shown = [c for c in names if c != "SQ_WAVES"]
-    print(f"Command: `{args.command}`\n")
+    # executed floating-point operations: a wave instruction is 64 lane
+    # operations, an FMA two flops
+    flop_sets = {p: [f"SQ_INSTS_VALU_{op}_{p}" for op in ("ADD", "MUL", "FMA", "TRANS")] for p in ("F64", "F32")}
+    have = {p: [c for c in cs if c in med] for p, cs in flop_sets.items()}
+
+    def flops(key, prec):
+        return 64.0 * sum(med[c].get(key, 0.0) * (2.0 if "_FMA_" in c else 1.0) for c in have[prec])
+    print(f"Commands: `{args.command}`\n")
     print(f"Durations: `{args.trace_command}`\n")
     print("Per-wave medians over the dispatches of each kernel (a wave is 64 elements in the element "
           "phase). VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x average duration), an "
           "estimate of the share of SIMD cycles spent issuing vector instructions: 4 cycles is what a "
           "wave64 FP64 FMA takes on a 16-lane SIMD (instructions that issue faster make it an "
           "overestimate) and 2.4 GHz is the peak clock (a lower clock makes it an underestimate).\n")
+    if have["F64"] or have["F32"]:
+        print("Executed flops per grid item (an element, or a node for the gather) = 64 lanes x "
+              "(ADD + MUL + 2 FMA + TRANS instructions) / grid size, counting every lane of a wave "
+              "instruction.\n")
+    extra = [p for p in ("F64", "F32") if have[p]]
     print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
-          " | avg us | VALU busy |")
-    print("|---|---:|---:|" + "---:|" * len(shown) + "---:|---:|")
+          "".join(f" | {p} flop/item" for p in extra) + " | avg us | VALU busy |")
+    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra)) + "---:|---:|")
+    rec = {"source_sha256": source_digest(), "command": args.command, "kernels": {}}
     for key in keys:
         waves = med["SQ_WAVES"][key]
         vals = " | ".join(f"{med[c].get(key, float('nan')) / waves:.1f}" for c in shown)
+        fl = "".join(f" | {flops(key, p) / key[1]:.1f}" for p in extra)
         d = dur.get(key[0])
         busy = (med["SQ_INSTS_VALU"][key] * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
                 if d and "SQ_INSTS_VALU" in med else float("nan"))
-        print(f"| `{key[0]}` | {key[1]} | {waves:.0f} | {vals} | "
+        print(f"| `{key[0]}` | {key[1]} | {waves:.0f} | {vals}{fl} | "
               f"{d * 1e6 if d else float('nan'):.1f} | {busy:.2f} |")
+        rec["kernels"][f"{key[0]} (grid {key[1]})"] = {
+            "waves": waves, "per_wave": {c: med[c].get(key) / waves for c in shown if key in med[c]},
+            **{f"{p.lower()}_flops": flops(key, p) for p in extra}}
+    if args.json_out:
+        # per benchmark call: the patch kernel of the mode plus its gather
+        calls = {}
+        for mode, tag in (("fwd", "0"), ("vjp", "1")):
+            ks = [k for k in keys if k[0] in (f"k_assemble_patch<double, 0, 0, {tag}, true>",
+                                              "k_gather_partials<double, 3>")]
+            if len(ks) == 2 and have["F64"]:
+                calls[mode] = {"kernels": [f"{k[0]} (grid {k[1]})" for k in ks],
+                               "fp64_flops": sum(flops(k, "F64") for k in ks)}
+        rec["calls"] = calls
+        with open(args.json_out, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
 
 
 def main():
@@ -175,11 +205,13 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     c = sub.add_parser("counters")
-    c.add_argument("pmc")
+    c.add_argument("pmc", nargs="+", help="counter CSVs of one or more --pmc passes over the same workload")
     c.add_argument("--trace", required=True, help="kernel_stats.csv of a --kernel-trace --stats run")
     c.add_argument("--command", required=True)
     c.add_argument("--trace-command", required=True)
     c.add_argument("--kernels", default=r"k_assemble_patch<\w+, 0, 0, [01], true>|k_gather_partials")
+    c.add_argument("--json-out", help="also write the per-kernel figures and the FP64 flops of the "
+                                      "benchmark calls as a JSON record tagged with the source digest")
     args = ap.parse_args()
     {"stats": stats, "traffic": traffic, "counters": counters}[args.cmd](args)
 
