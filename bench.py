@@ -400,6 +400,17 @@ def main():
                                   "sample": f"FP64 forward + VJP of the C oracle over the full {wl.n}^3 mesh "
                                             f"({ne} tets), median of {len(times)} passes "
                                             f"({sum(times):.1f} s of host work): {t_cpu:.2f} s wall each"}
+        # one host thread on the first eighth of the elements (the paper reports 1 core beside the node)
+        sub = np.ascontiguousarray(m.conn[: max(1, ne // 8)])
+        t1 = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.rhs(m.coords, sub, u_np, p_np, oprm, nthreads=1)
+            oracle.vjp(m.coords, sub, u_np, lam_np, oprm, nthreads=1)
+            t1.append(time.perf_counter() - t0)
+        result["cpu_baseline"]["one_thread"] = {
+            "value": sub.shape[0] / float(np.median(t1)), "unit": "elements/s", "cores": 1,
+            "sample": f"FP64 forward + VJP of the C oracle on the first {sub.shape[0]} tets, median of 3 passes"}
         # accuracy of the timed outputs against the oracle (user order)
         err = {"fp64_rhs": oracle.rel_l2(mesh.from_mesh_order(rhs).cpu().numpy(), r_ref),
                "fp64_grad": oracle.rel_l2(mesh.from_mesh_order(grad).cpu().numpy(), g_ref)}

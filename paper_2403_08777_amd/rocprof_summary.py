@@ -116,12 +116,21 @@ def traffic(args):
 def stats(args):
     with open(args.csv) as f:
         rows = list(csv.DictReader(f))
+    res = {}
+    if args.dispatches:
+        # LDS and scratch bytes per workgroup from the dispatch records of the same run
+        with open(args.dispatches) as f:
+            for r in csv.DictReader(f):
+                res.setdefault(short_name(r["Kernel_Name"]), (r["LDS_Block_Size"], r["Scratch_Size"]))
     print(f"Command: `{args.command}`\n")
-    print("| kernel | calls | avg us | min us | max us | total % |")
-    print("|---|---:|---:|---:|---:|---:|")
+    cols = " | LDS B | scratch B" if res else ""
+    print(f"| kernel | calls | avg us | min us | max us | total %{cols} |")
+    print("|---|---:|---:|---:|---:|---:|" + ("---:|" * 2 if res else ""))
     for r in rows[: args.top]:
-        print(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-              f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+        name = short_name(r["Name"])
+        extra = "".join(f" | {v}" for v in res.get(name, ("",) * 2)) if res else ""
+        print(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+              f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f}{extra} |")
 
 
 SIMDS = 256 * 4        # MI355X: 256 compute units, 4 SIMDs each
@@ -197,6 +206,7 @@ def main():
     s.add_argument("csv")
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=25)
+    s.add_argument("--dispatches", help="kernel_trace.csv of the same run, for LDS and scratch columns")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
