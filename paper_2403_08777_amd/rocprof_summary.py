@@ -168,14 +168,23 @@ def counters(args):
               "(ADD + MUL + 2 FMA + TRANS instructions) / grid size, counting every lane of a wave "
               "instruction.\n")
     extra = [p for p in ("F64", "F32") if have[p]]
+    lds_ratio = "SQ_LDS_BANK_CONFLICT" in med and "SQ_LDS_IDX_ACTIVE" in med
+    if lds_ratio:
+        print("Conflict share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: the fraction of the LDS's "
+              "indexed-active cycles spent stalled on bank conflicts (a ratio of two counters that "
+              "aggregate the same way).\n")
     print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
-          "".join(f" | {p} flop/item" for p in extra) + " | avg us | VALU busy |")
-    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra)) + "---:|---:|")
+          "".join(f" | {p} flop/item" for p in extra) + (" | conflict share" if lds_ratio else "") +
+          " | avg us | VALU busy |")
+    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra) + int(lds_ratio)) + "---:|---:|")
     rec = {"source_sha256": source_digest(), "command": args.command, "kernels": {}}
     for key in keys:
         waves = med["SQ_WAVES"][key]
         vals = " | ".join(f"{med[c].get(key, float('nan')) / waves:.1f}" for c in shown)
         fl = "".join(f" | {flops(key, p) / key[1]:.1f}" for p in extra)
+        if lds_ratio:
+            act = med["SQ_LDS_IDX_ACTIVE"].get(key, 0.0)
+            fl += f" | {med['SQ_LDS_BANK_CONFLICT'].get(key, 0.0) / act:.2f}" if act else " | -"
         d = dur.get(key[0])
         busy = (med["SQ_INSTS_VALU"][key] * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
                 if d and "SQ_INSTS_VALU" in med else float("nan"))
