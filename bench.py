@@ -113,10 +113,12 @@ def executed_rate(workload: str, mode: str, call_ms: float, ne: int):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    # The GPU's clocks rise over the first ~10 ms of sustained work: 200
+    # untimed steps reach the steady state, 200 timed steps take ~45 ms.
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="cube96_jit_perm")
-    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--scatter", default="auto", choices=["auto", "atomic", "patch"])
