@@ -169,14 +169,18 @@ def counters(args):
               "instruction.\n")
     extra = [p for p in ("F64", "F32") if have[p]]
     lds_ratio = "SQ_LDS_BANK_CONFLICT" in med and "SQ_LDS_IDX_ACTIVE" in med
+    l2 = next(((h, m) for h, m in (("TCC_HIT_sum", "TCC_MISS_sum"), ("TCC_HIT", "TCC_MISS"))
+               if h in med and m in med), None)
+    if l2:
+        print("L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS) over the kernel's L2 requests.\n")
     if lds_ratio:
         print("Conflict share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: the fraction of the LDS's "
               "indexed-active cycles spent stalled on bank conflicts (a ratio of two counters that "
               "aggregate the same way).\n")
     print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
           "".join(f" | {p} flop/item" for p in extra) + (" | conflict share" if lds_ratio else "") +
-          " | avg us | VALU busy |")
-    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra) + int(lds_ratio)) + "---:|---:|")
+          (" | L2 hit rate" if l2 else "") + " | avg us | VALU busy |")
+    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra) + int(lds_ratio) + int(bool(l2))) + "---:|---:|")
     rec = {"source_sha256": source_digest(), "command": args.command, "kernels": {}}
     for key in keys:
         waves = med["SQ_WAVES"][key]
@@ -185,6 +189,9 @@ def counters(args):
         if lds_ratio:
             act = med["SQ_LDS_IDX_ACTIVE"].get(key, 0.0)
             fl += f" | {med['SQ_LDS_BANK_CONFLICT'].get(key, 0.0) / act:.2f}" if act else " | -"
+        if l2:
+            hit, miss = med[l2[0]].get(key, 0.0), med[l2[1]].get(key, 0.0)
+            fl += f" | {hit / (hit + miss):.2f}" if hit + miss else " | -"
         d = dur.get(key[0])
         busy = (med["SQ_INSTS_VALU"][key] * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
                 if d and "SQ_INSTS_VALU" in med else float("nan"))
