@@ -199,6 +199,18 @@ def main():
     value = ne / (ms_per_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_per_step:.4f} ms/step (wall {wall_ms / args.steps:.4f}), "
         f"{value / 1e9:.2f} G elem/s fwd+VJP")
+    # the two calls' durations inside the step: the same K steps again with
+    # an event between the calls (each call's kernels and their boundary)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e0, e1, e2 in evs:
+        e0.record()
+        api.assemble_rhs(mesh, u, p, prm, out=rhs)
+        e1.record()
+        api.assemble_rhs_vjp(mesh, u, lam, prm, out=grad)
+        e2.record()
+    torch.cuda.synchronize()
+    in_step = {"fwd": sorted(e0.elapsed_time(e1) for e0, e1, _ in evs),
+               "vjp": sorted(e1.elapsed_time(e2) for _, e1, e2 in evs)}
 
     # the same step captured once in a HIP graph and replayed K times (no
     # host launch overhead between the four kernels); the replay must
@@ -234,8 +246,23 @@ def main():
     # launch stream; with atomic scatter, ACCUMULATE skips the zero-fill
     # kernel (the gather scatter has none)
     def kernel_ms(fn, reps):
+        """(mean, median, min, max) ms of one call: the mean of calls back to
+        back between one pair of events (no event between calls, as in the
+        timed steps; the median over five blocks, so that one stalled block
+        does not stand for the call), the others from calls timed one by one."""
         for _ in range(2):  # first launches of a kernel load its code object
             fn()
+        per = max(1, reps // 5)
+        blocks = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(per):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            blocks.append(a.elapsed_time(b) / per)
+        mean = float(np.median(blocks))
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
             a.record()
@@ -243,7 +270,7 @@ def main():
             b.record()
         torch.cuda.synchronize()
         t = sorted(a.elapsed_time(b) for a, b in evs)
-        return float(np.mean(t)), float(np.median(t)), t[0], t[-1]
+        return float(mean), float(np.median(t)), t[0], t[-1]
 
     scratch = torch.zeros_like(u)
     acc = mesh.info["scatter"] != "patch_gather"
@@ -251,13 +278,13 @@ def main():
     vjp_k = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, prm, out=scratch, accumulate=acc),
                       args.kernel_reps)
     fill_k = kernel_ms(lambda: scratch.zero_(), args.kernel_reps)
-    kernels = {
-        "fwd": {"mean_ms": fwd_k[0], "median_ms": fwd_k[1], "min_ms": fwd_k[2], "max_ms": fwd_k[3],
-                "alg_bytes": algorithmic_bytes(ne, nn, "fwd", 8)},
-        "vjp": {"mean_ms": vjp_k[0], "median_ms": vjp_k[1], "min_ms": vjp_k[2], "max_ms": vjp_k[3],
-                "alg_bytes": algorithmic_bytes(ne, nn, "vjp", 8)},
-        "zero_fill_equiv": {"mean_ms": fill_k[0]},
-    }
+    # mean/median/min/max: the call inside the timed step; alone_*: the same
+    # call repeated on its own (FP64-dense VJPs back to back run slower)
+    kernels = {k: {"mean_ms": float(np.mean(t)), "median_ms": float(np.median(t)), "min_ms": t[0], "max_ms": t[-1],
+                   "alone_mean_ms": ka[0], "alone_median_ms": ka[1],
+                   "alg_bytes": algorithmic_bytes(ne, nn, k, 8)}
+               for k, t, ka in (("fwd", in_step["fwd"], fwd_k), ("vjp", in_step["vjp"], vjp_k))}
+    kernels["zero_fill_equiv"] = {"mean_ms": fill_k[0]}
     eddy = wl.cs > 0
     for k in ("fwd", "vjp"):
         kk = kernels[k]
@@ -269,7 +296,8 @@ def main():
         kk["fp64_frac"] = kk["alg_TFs"] / FP64_PEAK_TFS
     dom = max(("fwd", "vjp"), key=lambda k: kernels[k]["mean_ms"])
     kd = kernels[dom]
-    log(f"[bench] kernels: fwd {fwd_k[0]:.4f} ms, vjp {vjp_k[0]:.4f} ms (dominant: {dom})")
+    log(f"[bench] calls in the step: fwd {kernels['fwd']['mean_ms']:.4f} ms, vjp {kernels['vjp']['mean_ms']:.4f} ms "
+        f"(alone: {fwd_k[0]:.4f}, {vjp_k[0]:.4f}; dominant: {dom})")
 
     forms = {"fp64_fwd_elems_per_s": kernels["fwd"]["elems_per_s"]}
     # mixed precision on the same mesh: fields FP32, geometry FP64
@@ -308,15 +336,15 @@ def main():
                                  ("rotational", wl.cs, "smagorinsky", "rotational"),
                                  ("emac", wl.cs, "smagorinsky", "emac")):
         vp = api.Params(wl.rho, wl.mu, cs, wl.body_force, model, conv)
-        # medians: one slow launch must not stand for the variant
-        tf = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, vp, out=scratch, accumulate=acc), args.kernel_reps)[1]
+        # means of calls back to back, as for the benchmark calls
+        tf = kernel_ms(lambda: api.assemble_rhs(mesh, u, p, vp, out=scratch, accumulate=acc), args.kernel_reps)[0]
         tv = kernel_ms(lambda: api.assemble_rhs_vjp(mesh, u, lam, vp, out=scratch, accumulate=acc),
-                       args.kernel_reps)[1]
+                       args.kernel_reps)[0]
         variants[tag] = {"eddy_model": model, "smagorinsky_cs": cs, "convective_form": conv, "fwd_ms": tf,
                          "vjp_ms": tv, "fwd_vjp_elems_per_s": ne / ((tf + tv) * 1e-3)}
     tj = kernel_ms(lambda: api.assemble_rhs_jvp(mesh, u, du, dpr, prm, out=scratch, accumulate=acc),
-                   args.kernel_reps)[1]
-    tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[1]
+                   args.kernel_reps)[0]
+    tp = kernel_ms(lambda: api.assemble_rhs_vjp_p(mesh, lam, prm, out=pr_g, accumulate=acc), args.kernel_reps)[0]
     variants["jvp"] = {"ms": tj, "elems_per_s": ne / (tj * 1e-3)}
     variants["vjp_p"] = {"ms": tp, "elems_per_s": ne / (tp * 1e-3)}
 
@@ -328,16 +356,16 @@ def main():
         u_req.grad = None
         api.NSAssembleRHS.apply(u_req, p, mesh, prm).backward(lam)
 
-    ta = kernel_ms(autograd_step, args.kernel_reps)[1]
+    ta = kernel_ms(autograd_step, args.kernel_reps)[0]
     variants["autograd_fwd_bwd"] = {"ms": ta, "elems_per_s": ne / (ta * 1e-3)}
     # explicit momentum stage u + dt R / (rho V^L) with a boundary Dirichlet
     # mask; with the gather scatter the update is fused into the gather kernel
     bnd = np.any((m.coords < 1e-12) | (m.coords > 1 - 1e-12), axis=1)
     mask = mesh.to_mesh_order(to_dev(np.where(bnd, 7.0, 0.0), torch.float64)).to(torch.uint8)
-    tu = kernel_ms(lambda: api.explicit_update(mesh, u, p, prm, 1e-3, mask, out=scratch), args.kernel_reps)[1]
+    tu = kernel_ms(lambda: api.explicit_update(mesh, u, p, prm, 1e-3, mask, out=scratch), args.kernel_reps)[0]
     variants["explicit_update"] = {"ms": tu, "elems_per_s": ne / (tu * 1e-3),
                                    "fused": mesh.info["scatter"] == "patch_gather",
-                                   "vs_forward_ms": tu - kernels["fwd"]["median_ms"]}
+                                   "vs_forward_ms": tu - kernels["fwd"]["mean_ms"]}
     log("[bench] variants (fwd+vjp G elem/s): " + ", ".join(
         f"{k} {v['fwd_vjp_elems_per_s'] / 1e9:.2f}" for k, v in variants.items() if "fwd_vjp_elems_per_s" in v)
         + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us, "
