@@ -137,7 +137,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the library assembles on one GPU; multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
