@@ -1,9 +1,11 @@
 """Benchmark of the Navier-Stokes momentum RHS assembly on one MI355X.
 
 One step = FP64 forward assembly + FP64 velocity VJP (the whole hot path:
-zero-fill, gather, geometry, gradients, element terms, scatter-add, adjoint) on
-the 96^3-cell jittered, relabelled cube (5,308,416 tets, 912,673 nodes), inputs
-resident in HBM in mesh order.  Prints one JSON line.
+gather, geometry, gradients, element terms, scatter-add, adjoint; the gather
+scatter writes every node, so no zero-fill is needed) on the 96^3-cell
+jittered, relabelled cube (5,308,416 tets, 912,673 nodes), inputs resident in
+HBM in mesh order.  Prints one JSON line; defaults: 200 untimed and 200 timed
+steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
