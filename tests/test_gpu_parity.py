@@ -295,3 +295,45 @@ def test_auto_halves_patches_for_a_tet_strip():
     with pytest.raises(api.NsasmError):
         api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev), scatter="patch_gather",
                  patch_elems=256)
+
+
+def _helix_strip(nt):
+    """Tetrahedra on a helix, tet k = (k, k+1, k+2, k+3): nt + 3 nodes."""
+    k = np.arange(nt + 3)
+    ang = 2 * np.pi * k / 3.3
+    coords = np.stack([0.05 * k, np.cos(ang), np.sin(ang)], axis=1)
+    conn = np.stack([k[:nt], k[:nt] + 1, k[:nt] + 2, k[:nt] + 3], axis=1).astype(np.int32)
+    return coords, conn
+
+
+@pytest.mark.parametrize("scatter", ["patch", "patch_gather"])
+def test_patch_with_the_maximum_256_nodes(scatter):
+    """253 strip tetrahedra form one patch that touches exactly 256 nodes:
+    every one-byte LDS position and every slot of the bank colouring is used.
+    FP64 forward and VJP at parity, mixed within its bound; one tetrahedron
+    more (257 nodes) makes the default fall back to 128-element patches."""
+    from paper_2403_08777_amd import api, synth
+
+    coords, conn = _helix_strip(253)
+    rng = np.random.default_rng(17)
+    u, p, lam = rng.standard_normal((256, 3)), rng.standard_normal(256), rng.standard_normal((256, 3))
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev), scatter=scatter)
+    info = mesh.info
+    log(f"256-node patch ({scatter}): {info}")
+    assert info["n_patches"] == 1 and info["max_patch_nodes"] == 256 and info["patch_elems"] == 256
+    prm = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    oprm = oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    for dtype, tol in ((torch.float64, TOL64), (torch.float32, 1e-5)):
+        tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype))
+        got = mesh.from_mesh_order(api.assemble_rhs(mesh, tm(u), tm(p), prm)).double().cpu().numpy()
+        g = mesh.from_mesh_order(api.assemble_rhs_vjp(mesh, tm(u), tm(lam), prm)).double().cpu().numpy()
+        er = oracle.rel_l2(got, oracle.rhs(coords, conn, u, p, oprm))
+        eg = oracle.rel_l2(g, oracle.vjp(coords, conn, u, lam, oprm))
+        log(f"  {str(dtype)[6:]}: rhs {er:.2e}, grad {eg:.2e}")
+        assert er <= tol and eg <= tol
+    mesh.close()
+    coords, conn = _helix_strip(254)
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev))
+    assert mesh.info["patch_elems"] == 128 and mesh.info["max_patch_nodes"] <= 256
+    mesh.close()
