@@ -337,3 +337,37 @@ def test_patch_with_the_maximum_256_nodes(scatter):
     mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev))
     assert mesh.info["patch_elems"] == 128 and mesh.info["max_patch_nodes"] <= 256
     mesh.close()
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+def test_high_valence_fan(scatter):
+    """200 tetrahedra around an axis share its two end nodes: each hub's run
+    holds 200 contributions in one patch (unstructured meshes have such
+    nodes; the cube meshes stop at 24).  FP64 and mixed forward + VJP."""
+    from paper_2403_08777_amd import api, synth
+
+    n = 200
+    ang = 2 * np.pi * np.arange(n) / n
+    ring = np.stack([np.cos(ang), np.sin(ang), 0.5 + 0.1 * np.sin(3 * ang)], axis=1)
+    coords = np.vstack([[0.0, 0.0, 0.0], [0.0, 0.0, 1.0], ring])
+    k = np.arange(n)
+    conn = np.stack([np.zeros(n, int), np.ones(n, int), 2 + k, 2 + (k + 1) % n], axis=1).astype(np.int32)
+    vol, _ = oracle.geometry(coords, conn)
+    assert vol.min() > 1e-4
+    rng = np.random.default_rng(19)
+    nn = coords.shape[0]
+    u, p, lam = rng.standard_normal((nn, 3)), rng.standard_normal(nn), rng.standard_normal((nn, 3))
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev), scatter=scatter)
+    log(f"fan ({scatter}): {mesh.info}")
+    prm = api.Params(1.0, 1e-2, 0.1, synth.BODY_FORCE)
+    oprm = oracle.Params(1.0, 1e-2, 0.1, synth.BODY_FORCE)
+    for dtype, tol in ((torch.float64, TOL64), (torch.float32, 1e-5)):
+        tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype))
+        got = mesh.from_mesh_order(api.assemble_rhs(mesh, tm(u), tm(p), prm)).double().cpu().numpy()
+        g = mesh.from_mesh_order(api.assemble_rhs_vjp(mesh, tm(u), tm(lam), prm)).double().cpu().numpy()
+        er = oracle.rel_l2(got, oracle.rhs(coords, conn, u, p, oprm))
+        eg = oracle.rel_l2(g, oracle.vjp(coords, conn, u, lam, oprm))
+        log(f"  {str(dtype)[6:]}: rhs {er:.2e}, grad {eg:.2e}")
+        assert er <= tol and eg <= tol
+    mesh.close()
