@@ -404,6 +404,21 @@ def main():
                   "device": torch.cuda.get_device_name(dev), "hip": getattr(torch.version, "hip", None)},
     }
 
+    # attainable HBM bandwidth: the library's Scale kernel (b = s a) over two
+    # 1 GiB FP64 arrays, far beyond the last-level cache; with the FP64 peak it
+    # gives the machine balance, as the paper does with its measured Scale rate
+    sc_a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    sc_b = torch.empty_like(sc_a)
+    sk = kernel_ms(lambda: api.stream_scale(sc_a, 3.0, out=sc_b), 20)
+    sc_bytes = 16 * sc_a.numel()
+    sc_gbs = sc_bytes / (sk[0] * 1e-3) / 1e9
+    result["hbm_scale"] = {"bytes_per_call": sc_bytes, "mean_ms": sk[0], "median_ms": sk[1], "GBs": sc_gbs,
+                           "frac_of_peak": sc_gbs / HBM_PEAK_GBS,
+                           "machine_balance_flop_per_byte": FP64_PEAK_TFS * 1e3 / sc_gbs}
+    log(f"[bench] Scale kernel over 2 x 1 GiB: {sk[0]:.3f} ms, {sc_gbs:.0f} GB/s "
+        f"({sc_gbs / HBM_PEAK_GBS:.2f} of peak; machine balance {FP64_PEAK_TFS * 1e3 / sc_gbs:.1f} flop/B)")
+    del sc_a, sc_b
+
     if args.copy_calibration:
         nbytes = 1 << 30
         a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)

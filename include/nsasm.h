@@ -296,6 +296,21 @@ nsasm_status nsasm_explicit_update(const nsasm_mesh *mesh, const nsasm_params *p
                                    nsasm_precision precision, double dt, const void *u, const void *p,
                                    const uint8_t *dirichlet_mask, void *rhs, void *u_new, void *stream);
 
+/*
+ * Attainable memory bandwidth: b[k] = s * a[k] for k < n, the Scale kernel
+ * whose measured rate, against the FP64 peak, gives the machine balance that
+ * the paper's roofline analysis uses (Sec. III-C).  One read and one write
+ * stream, 16 bytes moved per element; with arrays well beyond the last-level
+ * cache the rate is what a streaming kernel can draw from HBM.
+ * a, b : device, n doubles each; must not overlap (the caller owns both).
+ *        Both 16-byte aligned -> 16-byte accesses; otherwise 8-byte ones.
+ * n    : >= 0; 0 does nothing and checks no pointer.
+ * Asynchronous on stream.
+ * Errors: INVALID_ARGUMENT for n < 0, a NULL or non-device pointer, or
+ * overlapping arrays; DEVICE if the launch fails.
+ */
+nsasm_status nsasm_stream_scale(const double *a, double *b, int64_t n, double s, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *nsasm_last_error(void);
 

@@ -11,7 +11,7 @@ __version__ = "0.1.0"
 
 _LAZY = {
     "Mesh": "api", "Params": "api", "assemble_rhs": "api", "assemble_rhs_vjp": "api",
-    "NSAssembleRHS": "api", "FP64": "api", "MIXED": "api",
+    "NSAssembleRHS": "api", "FP64": "api", "MIXED": "api", "stream_scale": "api",
 }
 
 

@@ -70,10 +70,12 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_mesh_lumped_volume.argtypes = [vp, vp, vp]
     lib.nsasm_explicit_update.argtypes = [vp, ctypes.POINTER(_Params), st, ctypes.c_double, vp, vp, vp, vp, vp,
                                           vp]
+    lib.nsasm_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
                  "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp", "nsasm_assemble_rhs_vjp_p",
-                 "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update"):
+                 "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
+                 "nsasm_stream_scale"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -321,6 +323,20 @@ def explicit_update(mesh: Mesh, u: torch.Tensor, p: torch.Tensor, params: Params
     _check(lib.nsasm_explicit_update(mesh.handle, ctypes.byref(prm), prec, float(dt), u.data_ptr(), p.data_ptr(),
                                      None if dirichlet_mask is None else dirichlet_mask.data_ptr(),
                                      None if rhs is None else rhs.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def stream_scale(a: torch.Tensor, s: float, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """out = s * a for a 1-D float64 tensor (the Scale bandwidth kernel); out
+    must not overlap a."""
+    if not isinstance(a, torch.Tensor) or a.dim() != 1:
+        raise ValueError("a must be a 1-D torch.Tensor")
+    _dev(a, torch.float64, a.shape, "a")
+    if out is None:
+        out = torch.empty_like(a)
+    else:
+        _dev(out, torch.float64, a.shape, "out")
+    _check(lib.nsasm_stream_scale(a.data_ptr(), out.data_ptr(), a.numel(), float(s), _stream(stream)))
     return out
 
 

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["runtime.hip", "sort.hip", "mesh.hip", "assemble.hip"]
+SOURCES = ["runtime.hip", "sort.hip", "mesh.hip", "assemble.hip", "bandwidth.hip"]
 LIB = os.path.join(HERE, "libnsasm.so")
 ARCH = "gfx950"
 

@@ -99,6 +99,10 @@ def test_host_side_argument_checks():
     assert lib.nsasm_to_mesh_order(None, 3, 0, dummy, dummy, None) == 1
     assert lib.nsasm_from_mesh_order(None, 3, 0, dummy, dummy, None) == 1
     assert lib.nsasm_last_error()
+    # the Scale kernel: n < 0 is an error, n == 0 does nothing, NULL arrays are errors
+    assert lib.nsasm_stream_scale(None, None, -1, 2.0, None) == 1
+    assert lib.nsasm_stream_scale(None, None, 0, 2.0, None) == 0
+    assert lib.nsasm_stream_scale(None, None, 5, 2.0, None) == 1 and b"a is NULL" in lib.nsasm_last_error()
     assert lib.nsasm_mesh_destroy(None) == 0
     assert api.version() == "0.1.0"
 
