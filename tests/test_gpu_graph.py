@@ -4,7 +4,6 @@ times, with eager work and synchronisations between the replays; every
 replay must reproduce the eager results bit for bit (gather scatter: fixed
 summation order)."""
 
-import numpy as np
 import pytest
 import torch
 
