@@ -3,7 +3,6 @@ multiplication done by torch, in the 16-byte path (odd and even lengths,
 several blocks and a ragged last block) and the 8-byte path (misaligned
 arrays), nothing written past n, and the host-side refusals."""
 
-
 import pytest
 import torch
 
