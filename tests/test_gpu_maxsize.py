@@ -5,7 +5,8 @@ nodes (the lattice is cut inside its top cell layers).  The mesh is built on
 the GPU with torch; the FP64 forward and VJP are checked at sampled nodes
 against the oracle run on the sub-mesh of the elements around them (a node's
 value depends only on its own elements), and unreferenced nodes must come out
-exactly zero."""
+exactly zero; then the same in mixed precision, within 1e-5 of the FP64
+oracle."""
 
 import numpy as np
 import pytest
@@ -117,4 +118,15 @@ def test_maximum_element_count():
     er, eg = oracle.rel_l2(got_r, ref_r), oracle.rel_l2(got_g, ref_g)
     log(f"max-size sampled {len(referenced)} nodes over {len(e_idx)} elements: rhs rel_l2 {er:.2e}, vjp {eg:.2e}")
     assert er <= 1e-12 and eg <= 1e-12
+
+    # mixed precision on the same mesh: FP32 fields, error against the FP64 oracle
+    del rhs, grad
+    u32, p32, l32 = (mesh.to_mesh_order(t.float()) for t in (u, p, lam))
+    r32 = mesh.from_mesh_order(api.assemble_rhs(mesh, u32, p32, prm))
+    g32 = mesh.from_mesh_order(api.assemble_rhs_vjp(mesh, u32, l32, prm))
+    assert torch.all(r32[un] == 0) and torch.all(g32[un] == 0)
+    mr = oracle.rel_l2(r32[ridx].double().cpu().numpy(), ref_r)
+    mg = oracle.rel_l2(g32[ridx].double().cpu().numpy(), ref_g)
+    log(f"max-size mixed: rhs rel_l2 {mr:.2e}, vjp {mg:.2e}")
+    assert mr <= 1e-5 and mg <= 1e-5
     mesh.close()
