@@ -588,10 +588,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
     // The FP64 forward and VJP read u_a (and lambda_a) from LDS where they use
-    // them (twice each) instead of holding all four vertices in registers:
-    // 79 instead of 86 VGPRs (forward, six waves per SIMD instead of five) and
-    // 93 instead of 108 (VJP, five instead of four).  In FP32 the kernel
-    // already runs eight waves and the extra LDS reads would only cost.
+    // them (twice each) instead of holding all four vertices in registers,
+    // which keeps the forward at six waves per SIMD (five otherwise) and the
+    // VJP at five (four otherwise).  In FP32 the kernel already runs eight
+    // waves and the extra LDS reads would only cost.
     constexpr bool kLds = (MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value;
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
