@@ -63,3 +63,12 @@ def test_missing_or_broken_records(profile_dir):
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "exactly one GPU" in r.stderr
+
+
+def test_committed_profiles_match_the_current_sources():
+    """The committed traffic and VALU records were taken with the HIP sources
+    as they are now, so the bench line carries measured traffic and executed
+    flops; an edit under csrc/ must be followed by new profiles."""
+    for mode in ("fwd", "vjp"):
+        assert bench.measured_traffic("cube96_jit_perm", mode, "patch_gather") is not None
+        assert bench.executed_flops("cube96_jit_perm", mode) is not None
