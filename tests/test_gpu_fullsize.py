@@ -137,3 +137,25 @@ def test_jvp_and_pressure_vjp_full_96():
     ep = oracle.rel_l2(gp, oracle.vjp_p(m.coords, m.conn, lam))
     log(f"cube96 fp64 rel_l2: jvp {ej:.3e}, pressure vjp {ep:.3e}")
     assert ej <= 1e-12 and ep <= 1e-12
+
+
+@pytest.mark.parametrize("scatter", ["patch", "atomic"])
+def test_other_scatters_full_96(scatter):
+    """The scatter strategies the benchmark does not time, at full size: the
+    patch scheme with global atomics per patch node and the per-element atomic
+    scatter, FP64 forward and VJP against the oracle."""
+    from paper_2403_08777_amd import api
+
+    wl = synth.WORKLOADS["cube96_jit_perm"]
+    m, u, p, lam = synth.build(wl)
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.conn).to(dev), scatter=scatter)
+    assert mesh.info["scatter"] == scatter
+    prm, oprm = _params(wl)
+    r = _run(mesh, lambda ms, a, b: api.assemble_rhs(ms, a, b, prm), torch.float64, u, p)
+    g = _run(mesh, lambda ms, a, b: api.assemble_rhs_vjp(ms, a, b, prm), torch.float64, u, lam)
+    er = oracle.rel_l2(r, oracle.rhs(m.coords, m.conn, u, p, oprm))
+    eg = oracle.rel_l2(g, oracle.vjp(m.coords, m.conn, u, lam, oprm))
+    log(f"cube96 {scatter} fp64 rel_l2: rhs {er:.3e}, vjp {eg:.3e}")
+    mesh.close()
+    assert er <= 1e-12 and eg <= 1e-12
