@@ -122,7 +122,8 @@ def test_jvp_duality_full_96():
 
 def test_jvp_and_pressure_vjp_full_96():
     """At full size, element by element: the GPU JVP against the oracle's
-    complex-step JVP, and the GPU pressure VJP against the oracle's."""
+    complex-step JVP, and the GPU pressure VJP against the oracle's; FP64
+    to 1e-12 and mixed precision within 1e-5."""
     from paper_2403_08777_amd import api
 
     wl, m, u, p, lam, mesh = _case("cube96_jit_perm")
@@ -133,10 +134,18 @@ def test_jvp_and_pressure_vjp_full_96():
     tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
     jv = mesh.from_mesh_order(api.assemble_rhs_jvp(mesh, tm(u), tm(du), tm(dp), prm)).cpu().numpy()
     gp = mesh.from_mesh_order(api.assemble_rhs_vjp_p(mesh, tm(lam), prm)).cpu().numpy()
-    ej = oracle.rel_l2(jv, oracle.jvp(m.coords, m.conn, u, p, du, dp, oprm))
-    ep = oracle.rel_l2(gp, oracle.vjp_p(m.coords, m.conn, lam))
+    j_ref = oracle.jvp(m.coords, m.conn, u, p, du, dp, oprm)
+    p_ref = oracle.vjp_p(m.coords, m.conn, lam)
+    ej, ep = oracle.rel_l2(jv, j_ref), oracle.rel_l2(gp, p_ref)
     log(f"cube96 fp64 rel_l2: jvp {ej:.3e}, pressure vjp {ep:.3e}")
     assert ej <= 1e-12 and ep <= 1e-12
+    # mixed precision: FP32 fields, against the FP64 oracle
+    t32 = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32))
+    jv32 = mesh.from_mesh_order(api.assemble_rhs_jvp(mesh, t32(u), t32(du), t32(dp), prm)).double().cpu().numpy()
+    gp32 = mesh.from_mesh_order(api.assemble_rhs_vjp_p(mesh, t32(lam), prm)).double().cpu().numpy()
+    mj, mp = oracle.rel_l2(jv32, j_ref), oracle.rel_l2(gp32, p_ref)
+    log(f"cube96 mixed rel_l2: jvp {mj:.3e}, pressure vjp {mp:.3e}")
+    assert mj <= 1e-5 and mp <= 1e-5
 
 
 @pytest.mark.parametrize("scatter", ["patch", "atomic"])
