@@ -144,7 +144,7 @@ typedef struct {
 typedef struct {
     int64_t n_nodes;
     int64_t n_elems;
-    int32_t scatter;         /* resolved nsasm_scatter: ATOMIC or PATCH */
+    int32_t scatter;         /* resolved nsasm_scatter: ATOMIC, PATCH or PATCH_GATHER */
     int32_t renumbered;      /* 1 if mesh order differs from user order */
     int32_t n_patches;       /* 0 when scatter == ATOMIC */
     int32_t patch_elems;
