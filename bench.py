@@ -296,6 +296,9 @@ def main():
         kk["alg_TFs"] = kk["alg_flops"] / (kk["mean_ms"] * 1e-3) / 1e12
         kk["hbm_frac"] = kk["alg_GBs"] / HBM_PEAK_GBS
         kk["fp64_frac"] = kk["alg_TFs"] / FP64_PEAK_TFS
+        # measured HBM bytes of the call (committed counter record), when current
+        tb = measured_traffic(wl.name, k, mesh.info["scatter"])
+        kk["traffic_GBs"] = tb / (kk["mean_ms"] * 1e-3) / 1e9 if tb else None
     dom = max(("fwd", "vjp"), key=lambda k: kernels[k]["mean_ms"])
     kd = kernels[dom]
     log(f"[bench] calls in the step: fwd {kernels['fwd']['mean_ms']:.4f} ms, vjp {kernels['vjp']['mean_ms']:.4f} ms "
@@ -417,6 +420,11 @@ def main():
                            "machine_balance_flop_per_byte": FP64_PEAK_TFS * 1e3 / sc_gbs}
     log(f"[bench] Scale kernel over 2 x 1 GiB: {sk[0]:.3f} ms, {sc_gbs:.0f} GB/s "
         f"({sc_gbs / HBM_PEAK_GBS:.2f} of peak; machine balance {FP64_PEAK_TFS * 1e3 / sc_gbs:.1f} flop/B)")
+    # each call's bandwidth also as a fraction of what the Scale kernel draws
+    for k in ("fwd", "vjp"):
+        kk = kernels[k]
+        kk["alg_frac_of_scale"] = kk["alg_GBs"] / sc_gbs
+        kk["traffic_frac_of_scale"] = kk["traffic_GBs"] / sc_gbs if kk["traffic_GBs"] else None
     del sc_a, sc_b
 
     if args.copy_calibration:
