@@ -56,7 +56,7 @@ typedef enum {
     NSASM_OK = 0,
     NSASM_ERR_INVALID_ARGUMENT = 1,   /* null/host pointer, bad size, bad enum */
     NSASM_ERR_BAD_CONNECTIVITY = 2,   /* node id out of range or repeated in a tet */
-    NSASM_ERR_DEGENERATE_ELEMENT = 3, /* det J == 0 (or not finite) */
+    NSASM_ERR_DEGENERATE_ELEMENT = 3, /* det J within rounding of zero, subnormal, or not finite */
     NSASM_ERR_OUT_OF_MEMORY = 4,
     NSASM_ERR_DEVICE = 5,             /* HIP runtime / launch failure */
     NSASM_ERR_UNSUPPORTED = 6         /* valid request the mesh cannot serve */
@@ -69,7 +69,9 @@ typedef enum {
 } nsasm_precision;
 
 typedef enum {
-    NSASM_SCATTER_AUTO = 0,   /* PATCH when the mesh allows it, else ATOMIC */
+    NSASM_SCATTER_AUTO = 0,   /* PATCH_GATHER when the mesh allows it, else ATOMIC;
+                                 with PATCH_GATHER, assembly calls on one mesh
+                                 must not overlap in time (see below) */
     NSASM_SCATTER_ATOMIC = 1, /* one thread per element, 12 global atomic adds */
     NSASM_SCATTER_PATCH = 2,  /* element patches staged through LDS: nodes gathered
                                  once per patch, element contributions summed per
@@ -167,40 +169,56 @@ typedef struct {
  * opts    : may be NULL (defaults above).
  * out     : receives the handle; set to NULL on failure (nothing is leaked).
  * Errors  : INVALID_ARGUMENT (null/host pointers, n <= 0, n_nodes >= 2^31,
- *           n_elems >= 2^29, bad options), BAD_CONNECTIVITY, DEGENERATE_ELEMENT,
- *           OUT_OF_MEMORY, DEVICE; UNSUPPORTED when scatter = PATCH is asked for
- *           and some patch has more than 256 distinct nodes.
+ *           n_elems >= 2^29, bad options), BAD_CONNECTIVITY, DEGENERATE_ELEMENT
+ *           (|det J| <= 64 eps |d1||d2||d3| with d_k = x_k - x_0, a subnormal
+ *           det J or a non-finite vertex: within rounding of a flat element,
+ *           where 1/det J would be noise), OUT_OF_MEMORY, DEVICE; UNSUPPORTED
+ *           when scatter = PATCH is asked for and some patch has more than 256
+ *           distinct nodes.
  */
 nsasm_status nsasm_mesh_create(const double *coords, int64_t n_nodes, const int32_t *conn,
                                int64_t n_elems, const nsasm_mesh_options *opts, void *stream,
                                nsasm_mesh **out);
 
-/* Free a mesh and its device buffers (synchronises the device).  NULL is OK. */
+/* Library helper, no passage of the paper.  Free a mesh and its device
+ * buffers (synchronises the device).  NULL is OK. */
 nsasm_status nsasm_mesh_destroy(nsasm_mesh *mesh);
 
-/* Sizes and layout decisions of a mesh (host struct). */
+/* Library helper, no passage of the paper.  Sizes and layout decisions of a
+ * mesh, written to the caller's host struct `info`.  Errors: INVALID_ARGUMENT
+ * for a NULL mesh or info. */
 nsasm_status nsasm_mesh_info(const nsasm_mesh *mesh, nsasm_mesh_info_t *info);
 
-/* mesh_id_of_user: device, n_nodes int32; entry k is the mesh-order index of
- * user node k (identity when not renumbered).  Asynchronous on stream. */
+/* Library helper, no passage of the paper (the renumbering of
+ * nsasm_mesh_create).  mesh_id_of_user: device, n_nodes int32 (caller-owned);
+ * entry k is the mesh-order index of user node k (identity when not
+ * renumbered).  Asynchronous on stream.  Errors: INVALID_ARGUMENT (NULL mesh,
+ * non-device pointer), DEVICE. */
 nsasm_status nsasm_mesh_permutation(const nsasm_mesh *mesh, int32_t *mesh_id_of_user, void *stream);
 
-/* Internal connectivity: conn_mesh (device, n_elems x 4 int32, mesh node ids,
- * mesh element order) and user_elem (device, n_elems int32, user index of each
- * mesh-order element).  Either may be NULL.  Asynchronous on stream. */
+/* Library helper, no passage of the paper.  Internal connectivity: conn_mesh
+ * (device, n_elems x 4 int32, mesh node ids, mesh element order) and
+ * user_elem (device, n_elems int32, user index of each mesh-order element),
+ * both caller-owned.  Either may be NULL.  Asynchronous on stream.  Errors:
+ * INVALID_ARGUMENT (NULL mesh, non-device pointer), DEVICE. */
 nsasm_status nsasm_mesh_connectivity(const nsasm_mesh *mesh, int32_t *conn_mesh, int32_t *user_elem,
                                      void *stream);
 
-/* Reorder a per-node field with ncomp (1..16) components between user order
- * and mesh order: mesh_ordered[perm[k]] = user[k] and back.  Element type per
- * precision (double / float).  Buffers must not overlap.  Asynchronous. */
+/* Library helper, no passage of the paper.  Reorder a per-node field with
+ * ncomp (1..16) components between user order and mesh order:
+ * mesh_ordered[perm[k]] = user[k] and back.  Both arrays are device,
+ * n_nodes x ncomp, caller-owned, element type per precision (double / float),
+ * and must not overlap.  Asynchronous on stream.  Errors: INVALID_ARGUMENT
+ * (NULL mesh, bad ncomp or precision, non-device or identical pointers),
+ * DEVICE. */
 nsasm_status nsasm_to_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_precision precision,
                                  const void *user, void *mesh_ordered, void *stream);
 nsasm_status nsasm_from_mesh_order(const nsasm_mesh *mesh, int32_t ncomp, nsasm_precision precision,
                                    const void *mesh_ordered, void *user, void *stream);
 
 /*
- * Assemble the momentum RHS (definition at the top of this file).
+ * Assemble the momentum RHS (definition at the top of this file; Sec. II for
+ * the operation, Sec. V-A and V-B for its per-element form).
  * u   : device, n_nodes x 3, mesh order.    p : device, n_nodes, mesh order.
  * rhs : device, n_nodes x 3, mesh order; overwritten (or added to with
  *       NSASM_ACCUMULATE).  Must not overlap u or p.
@@ -222,6 +240,8 @@ nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *para
 /*
  * Velocity vector-Jacobian product of the assembled RHS:
  *   grad_u = (d rhs / d u)^T adjoint,
+ * the transpose of the linearisation of the Sec. II / V-B operation (the
+ * paper states no adjoint; this is its exact derivative),
  * recomputing the element quantities (nothing is stored by the forward call).
  * The pressure and body-force terms do not depend on u.  The eddy viscosity
  * is differentiated as stated at nsasm_params.
@@ -236,7 +256,8 @@ nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *
 
 /*
  * Pressure vector-Jacobian product of the assembled RHS:
- *   grad_p = (d rhs / d p)^T adjoint.
+ *   grad_p = (d rhs / d p)^T adjoint
+ * (exact derivative of the Sec. II / V-B operation; the paper states none).
  * The RHS depends on p only through the pressure-gradient term, which is
  * linear in p (per element -(V/4) grad p at every vertex), so grad_p does not
  * depend on u and the eddy viscosity plays no part.
@@ -250,7 +271,8 @@ nsasm_status nsasm_assemble_rhs_vjp_p(const nsasm_mesh *mesh, const nsasm_params
                                       void *stream);
 
 /*
- * Jacobian-vector product (directional derivative) of the assembled RHS:
+ * Jacobian-vector product (directional derivative) of the assembled RHS
+ * (exact derivative of the Sec. II / V-B operation; the paper states none):
  *   drhs = (d rhs / d u) du + (d rhs / d p) dp,
  * recomputing the element quantities; the eddy viscosity is differentiated as
  * stated at nsasm_params.  This is the product a Jacobian-free Newton-Krylov
@@ -267,8 +289,10 @@ nsasm_status nsasm_assemble_rhs_jvp(const nsasm_mesh *mesh, const nsasm_params *
 /*
  * Lumped volume of every node, V^L_n = sum over the elements e containing n
  * of V_e / 4: the row sums of the P1 mass matrix divided by the density,
- * computed once at mesh creation.  lumped: device, n_nodes doubles, mesh
- * order.  Asynchronous on stream.
+ * computed once at mesh creation (the mass of the explicit momentum stage of
+ * Sec. II).  lumped: device, n_nodes doubles, mesh order, caller-owned; 0 at
+ * nodes no element references.  Asynchronous on stream.  Errors:
+ * INVALID_ARGUMENT (NULL mesh, non-device pointer), DEVICE.
  */
 nsasm_status nsasm_mesh_lumped_volume(const nsasm_mesh *mesh, double *lumped, void *stream);
 
@@ -279,7 +303,8 @@ nsasm_status nsasm_mesh_lumped_volume(const nsasm_mesh *mesh, double *lumped, vo
  *   rhs   = the assembled RHS of (u, p)       (as nsasm_assemble_rhs)
  *   u_new[n][i] = u[n][i] + dt rhs[n][i] / (rho V^L_n)   if bit i of mask[n] is 0,
  *   u_new[n][i] = u[n][i]                               if it is 1
- * (Dirichlet components keep the value the caller stored in u).
+ * (Dirichlet components keep the value the caller stored in u).  A node that
+ * no element references has V^L_n = 0 and rhs 0 and keeps u_new = u.
  * u              : device, n_nodes x 3, mesh order.   p : device, n_nodes.
  * dirichlet_mask : device, n_nodes bytes (bits 0..2 = x, y, z), or NULL (none).
  * rhs            : device, n_nodes x 3, receives the assembled RHS; may be NULL
@@ -311,10 +336,27 @@ nsasm_status nsasm_explicit_update(const nsasm_mesh *mesh, const nsasm_params *p
  */
 nsasm_status nsasm_stream_scale(const double *a, double *b, int64_t n, double s, void *stream);
 
-/* Message for the last non-OK status on this thread ("" if none). */
+/*
+ * Library helper for measurement, no passage of the paper (the paper times
+ * its kernels one by one, Sec. III-A; this lets a caller do the same with HIP
+ * events).  event: a hipEvent_t created by the caller (who keeps owning it),
+ * or NULL to cancel.  The next assembly call made on this thread
+ * (nsasm_assemble_rhs, _vjp, _vjp_p, _jvp, nsasm_explicit_update) records it
+ * on its stream right after its element kernel: with PATCH_GATHER between the
+ * patch kernel and the node-gather kernel, with the one-kernel scatters after
+ * that kernel.  The call consumes the event whether it succeeds or not.  The
+ * event is not recorded by nsasm_mesh_create or any other function.  Always
+ * returns NSASM_OK.
+ */
+nsasm_status nsasm_set_phase_event(void *event);
+
+/* Library helper, no passage of the paper.  Message for the last non-OK
+ * status on this thread ("" if none); the string is owned by the library and
+ * valid until the next call on this thread. */
 const char *nsasm_last_error(void);
 
-/* Library version string, e.g. "0.1.0". */
+/* Library helper, no passage of the paper.  Library version string, e.g.
+ * "0.2.0" (static storage). */
 const char *nsasm_version(void);
 
 #ifdef __cplusplus

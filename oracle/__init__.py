@@ -230,10 +230,15 @@ def explicit_update(coords, conn, u, p, prm: Params, dt, mask=None):
         u_new[n, i] = u[n, i] + dt R[n, i] / (rho V^L_n)
     for free components, and u_new[n, i] = u[n, i] where bit i of mask[n] is
     set (Dirichlet-constrained components keep the value the caller put in
-    u).  Returns (u_new, R)."""
+    u).  A node that no element references has no mass (V^L_n = 0) and no
+    residual; the stage leaves it unchanged (u_new = u), the reading taken
+    where the update would otherwise be 0/0.  Returns (u_new, R)."""
     u = _f64(u)
     R = rhs(coords, conn, u, p, prm)
-    step = u + dt * R / (prm.rho * lumped_volume(coords, conn))[:, None]
+    vl = lumped_volume(coords, conn)
+    inv_mass = np.zeros_like(vl)
+    np.divide(1.0, prm.rho * vl, out=inv_mass, where=vl > 0)
+    step = u + dt * R * inv_mass[:, None]
     if mask is None:
         return step, R
     m = np.asarray(mask, dtype=np.uint8)

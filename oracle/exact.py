@@ -112,19 +112,22 @@ def assemble_rhs(coords, conn, u, p, rho, mu, f, mu_elem=None, form="advective")
     return out
 
 
-def assemble_vjp(coords, conn, u, lam, rho, mu, f, form="advective"):
+def assemble_vjp(coords, conn, u, lam, rho, mu, f, form="advective", mu_elem=None):
     """Exact (dR/du)^T lam for mu_t = 0, by unit-step central differences of
-    the quadratic element functional lam_e . R^e(u_e) (exact for quadratics)."""
+    the quadratic element functional lam_e . R^e(u_e) (exact for quadratics).
+    ``mu_elem`` optionally gives each element its own viscosity, held fixed
+    (the derivative of a velocity-dependent viscosity is not included)."""
     nn = len(coords)
     zero_p = [Fraction(0)] * 4
     out = [[Fraction(0)] * 3 for _ in range(nn)]
-    for tet in conn:
+    for e, tet in enumerate(conn):
         ids = [int(t) for t in tet]
         xe = [coords[n] for n in ids]
         le = [lam[n] for n in ids]
+        mu_e = mu if mu_elem is None else mu_elem[e]
 
         def functional(ue):
-            re = element_rhs(xe, ue, zero_p, rho, mu, f, form)
+            re = element_rhs(xe, ue, zero_p, rho, mu_e, f, form)
             return sum(le[a][i] * re[a][i] for a in range(4) for i in range(3))
 
         base = [list(u[n]) for n in ids]

@@ -7,7 +7,7 @@ this package only marshals arguments to it.  Importing the GPU-facing names
 been built.  ``synth`` (synthetic inputs) needs only numpy.
 """
 
-__version__ = "0.1.0"
+__version__ = "0.2.0"
 
 _LAZY = {
     "Mesh": "api", "Params": "api", "assemble_rhs": "api", "assemble_rhs_vjp": "api",

@@ -71,11 +71,12 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_explicit_update.argtypes = [vp, ctypes.POINTER(_Params), st, ctypes.c_double, vp, vp, vp, vp, vp,
                                           vp]
     lib.nsasm_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
+    lib.nsasm_set_phase_event.argtypes = [vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
                  "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp", "nsasm_assemble_rhs_vjp_p",
                  "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
-                 "nsasm_stream_scale"):
+                 "nsasm_stream_scale", "nsasm_set_phase_event"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -340,10 +341,27 @@ def stream_scale(a: torch.Tensor, s: float, out: torch.Tensor = None, stream=Non
     return out
 
 
+def set_phase_event(event) -> None:
+    """Have the next assembly call on this thread record ``event`` (a
+    ``torch.cuda.Event`` already recorded once, so that its HIP event exists,
+    or None to cancel) on its stream between its element kernel and its gather
+    kernel (nsasm_set_phase_event)."""
+    if event is None:
+        _check(lib.nsasm_set_phase_event(None))
+        return
+    handle = event.cuda_event
+    if not handle:
+        raise ValueError("record the event once before passing it (its HIP event is created lazily)")
+    _check(lib.nsasm_set_phase_event(handle))
+
+
 class NSAssembleRHS(torch.autograd.Function):
     """rhs = NSAssembleRHS.apply(u, p, mesh, params); differentiable in u and p,
     in reverse mode (hand-written VJP kernels) and forward mode (the JVP
-    kernel).  Element quantities are recomputed, never stored."""
+    kernel).  Element quantities are recomputed, never stored.  The backward
+    is differentiable once: asking for a second-order derivative through it
+    (create_graph=True, then another backward) raises instead of silently
+    dropping the terms the kernels do not provide."""
 
     @staticmethod
     def forward(ctx, u, p, mesh, params):
@@ -354,6 +372,7 @@ class NSAssembleRHS(torch.autograd.Function):
         return assemble_rhs(mesh, u, p, params)
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, grad_rhs):
         (u,) = ctx.saved_tensors
         lam = grad_rhs.contiguous()

@@ -94,20 +94,8 @@ __device__ inline float cube_root(float v) { return cbrtf(v); }
 
 // Shape-function gradients and volume, always in FP64.
 __device__ inline void tet_geometry(const double (&xe)[4][3], double (&gN)[4][3], double &vol) {
-    double d1[3], d2[3], d3[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        d1[i] = xe[1][i] - xe[0][i];
-        d2[i] = xe[2][i] - xe[0][i];
-        d3[i] = xe[3][i] - xe[0][i];
-    }
-    const double c1[3] = {d2[1] * d3[2] - d2[2] * d3[1], d2[2] * d3[0] - d2[0] * d3[2],
-                          d2[0] * d3[1] - d2[1] * d3[0]};
-    const double c2[3] = {d3[1] * d1[2] - d3[2] * d1[1], d3[2] * d1[0] - d3[0] * d1[2],
-                          d3[0] * d1[1] - d3[1] * d1[0]};
-    const double c3[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2],
-                          d1[0] * d2[1] - d1[1] * d2[0]};
-    const double det = d1[0] * c1[0] + d1[1] * c1[1] + d1[2] * c1[2];
+    double c1[3], c2[3], c3[3], d1[3];
+    const double det = tet_adjugate(xe, c1, c2, c3, d1);
     // 1/det: hardware reciprocal estimate refined by two Newton-Raphson steps
     // (each squares the relative error), enough for full double precision for
     // the finite, non-zero determinants a validated mesh has.
@@ -726,11 +714,18 @@ __global__ __launch_bounds__(kThreads) void k_gather_partials(int64_t nn, const 
     for (int i = 0; i < NOUT; ++i) out[NOUT * n + i] = accumulate ? out[NOUT * n + i] + acc[i] : acc[i];
 }
 
+// dt / (rho V^L_n), the explicit-update weight of node n; 0 for a node that no
+// element references (V^L_n = 0: no mass and no residual, so u stays).
+template <typename T>
+__device__ inline T update_weight(double lumped, double rho, double dt) {
+    return lumped > 0.0 ? static_cast<T>(dt / (rho * lumped)) : T(0);
+}
+
 // Explicit momentum stage fused into the gather: rhs_n is summed from the
 // patch partials as in k_gather_partials, optionally stored, and
 //   u_new[n, i] = u[n, i] + dt rhs[n, i] / (rho V^L_n)
 // for components whose bit i of mask[n] is clear (u_new[n, i] = u[n, i]
-// otherwise).  u_new may be u itself: each thread reads and writes only its
+// otherwise, and at nodes with V^L_n = 0).  u_new may be u itself: each thread reads and writes only its
 // own node.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gather_update(int64_t nn, const int32_t *__restrict__ ref_off,
@@ -746,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void k_gather_update(int64_t nn, const in
 #pragma unroll
         for (int i = 0; i < 3; ++i) rhs[3 * n + i] = acc[i];
     }
-    const T w = static_cast<T>(dt / (rho * lumped[n]));
+    const T w = update_weight<T>(lumped[n], rho, dt);
     const unsigned fixed = mask ? mask[n] : 0u;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -762,7 +757,7 @@ __global__ __launch_bounds__(kThreads) void k_update(int64_t nn, const T *__rest
                                                      const T *u, const uint8_t *__restrict__ mask, T *u_new) {
     const int64_t n = xcd_tile(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
     if (n >= nn) return;
-    const T w = static_cast<T>(dt / (rho * lumped[n]));
+    const T w = update_weight<T>(lumped[n], rho, dt);
     const unsigned fixed = mask ? mask[n] : 0u;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -822,11 +817,20 @@ struct Update {
     T *u_new;
 };
 
+// Recorded on the launch stream after the element kernel of a call (see
+// nsasm_set_phase_event); null for none.
+nsasm_status record_phase(hipEvent_t phase, hipStream_t s) {
+    if (!phase) return NSASM_OK;
+    hipError_t err = hipEventRecord(phase, s);
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, "hipEventRecord of the phase event");
+}
+
 // With the gather scatter and `up` set, the gather kernel applies the
-// explicit update instead of writing `out`.
+// explicit update instead of writing `out`.  `phase` (may be null) is
+// recorded between the element kernel and the gather kernel.
 template <typename T, int EDDY, int CONV, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, T *out, bool accumulate,
-                    const Update<T> *up, hipStream_t s) {
+                    const Update<T> *up, hipEvent_t phase, hipStream_t s) {
     constexpr int NOUT = Fields<MODE>::NOUT;
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
         T *partial = reinterpret_cast<T *>(m->partial);
@@ -835,6 +839,7 @@ nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, 
             m->elem_loc, m->x, F, kp, partial);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
+        NSASM_TRY(record_phase(phase, s));
         const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
         if constexpr (MODE == kForward) {
             if (up) {
@@ -857,30 +862,32 @@ nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, 
                                                                                    kp, out);
     }
     hipError_t err = hipGetLastError();
-    return err == hipSuccess ? NSASM_OK : hip_fail(err, "assembly kernel launch");
+    if (err != hipSuccess) return hip_fail(err, "assembly kernel launch");
+    return m->scatter == NSASM_SCATTER_PATCH_GATHER ? NSASM_OK : record_phase(phase, s);
 }
 
 template <typename T, int CONV, int MODE>
 nsasm_status launch_eddy(const nsasm_mesh *m, const nsasm_params &p, const KParams<T> &kp, NodeFields<T> F, T *o,
-                         const Update<T> *up, hipStream_t s) {
+                         const Update<T> *up, hipEvent_t ph, hipStream_t s) {
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
-        return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, s);
-    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, CONV, MODE>(m, kp, F, o, accumulate, up, s);
-    return launch<T, kNoEddy, CONV, MODE>(m, kp, F, o, accumulate, up, s);
+        return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
+    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
+    return launch<T, kNoEddy, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
 }
 
 // Physics selection (convective form, eddy viscosity) of a launch.
 template <typename T, int MODE>
 nsasm_status dispatch(const nsasm_mesh *m, const nsasm_params &p, NodeFields<T> F, T *o, const Update<T> *up,
-                    hipStream_t s) {
+                      hipEvent_t ph, hipStream_t s) {
     const KParams<T> kp = kernel_params<T>(p);
     if constexpr (MODE == kVjpP) {
         // the pressure term depends on neither the viscosity nor the convective form
-        return launch<T, kNoEddy, kAdvective, MODE>(m, kp, F, o, (p.flags & NSASM_ACCUMULATE) != 0, up, s);
+        return launch<T, kNoEddy, kAdvective, MODE>(m, kp, F, o, (p.flags & NSASM_ACCUMULATE) != 0, up, ph, s);
     } else {
-        if (p.convective_form != NSASM_CONVECTIVE_ADVECTIVE) return launch_eddy<T, kGeneral, MODE>(m, p, kp, F, o, up, s);
-        return launch_eddy<T, kAdvective, MODE>(m, p, kp, F, o, up, s);
+        if (p.convective_form != NSASM_CONVECTIVE_ADVECTIVE)
+            return launch_eddy<T, kGeneral, MODE>(m, p, kp, F, o, up, ph, s);
+        return launch_eddy<T, kAdvective, MODE>(m, p, kp, F, o, up, ph, s);
     }
 }
 
@@ -894,27 +901,27 @@ nsasm_status fill_zero(T *o, int64_t n, hipStream_t s) {
 
 template <typename T, int MODE>
 nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *fa, const void *fb, const void *fc,
-                 void *out, hipStream_t s) {
+                 void *out, hipEvent_t ph, hipStream_t s) {
     T *o = static_cast<T *>(out);
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     // the gather kernel writes every node, so it needs no zero-fill
     if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER)
         NSASM_TRY(fill_zero(o, Fields<MODE>::NOUT * m->n_nodes, s));
     const NodeFields<T> F{static_cast<const T *>(fa), static_cast<const T *>(fb), static_cast<const T *>(fc)};
-    return dispatch<T, MODE>(m, p, F, o, nullptr, s);
+    return dispatch<T, MODE>(m, p, F, o, nullptr, ph, s);
 }
 
 // Forward assembly and the explicit update: fused into the gather kernel with
 // the gather scatter, else assembled into `rhs` and updated by k_update.
 template <typename T>
 nsasm_status run_update(const nsasm_mesh *m, const nsasm_params &p, double dt, const void *u, const void *pr,
-                        const uint8_t *mask, void *rhs, void *u_new, hipStream_t s) {
+                        const uint8_t *mask, void *rhs, void *u_new, hipEvent_t ph, hipStream_t s) {
     const NodeFields<T> F{static_cast<const T *>(u), nullptr, static_cast<const T *>(pr)};
     T *r = static_cast<T *>(rhs);
     const Update<T> up{p.rho, dt, static_cast<const T *>(u), mask, r, static_cast<T *>(u_new)};
-    if (m->scatter == NSASM_SCATTER_PATCH_GATHER) return dispatch<T, kForward>(m, p, F, nullptr, &up, s);
+    if (m->scatter == NSASM_SCATTER_PATCH_GATHER) return dispatch<T, kForward>(m, p, F, nullptr, &up, ph, s);
     NSASM_TRY(fill_zero(r, 3 * m->n_nodes, s));
-    NSASM_TRY((dispatch<T, kForward>(m, p, F, r, nullptr, s)));
+    NSASM_TRY((dispatch<T, kForward>(m, p, F, r, nullptr, ph, s)));
     const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
     k_update<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, r, m->lumped, p.rho, dt, up.u, mask, up.u_new);
     hipError_t err = hipGetLastError();
@@ -933,6 +940,7 @@ struct Arg {
 template <int MODE>
 nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, Arg a, Arg b, Arg c,
                    Arg out, void *stream) {
+    const hipEvent_t ph = take_phase_event();  // consumed by this call, whatever its outcome
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
     if (prec != NSASM_FP64 && prec != NSASM_MIXED)
@@ -949,14 +957,15 @@ nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precis
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *o = const_cast<void *>(out.ptr);
-    const nsasm_status st = (prec == NSASM_FP64) ? run<double, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, s)
-                                                 : run<float, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, s);
+    const nsasm_status st = (prec == NSASM_FP64) ? run<double, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s)
+                                                 : run<float, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s);
     if (st == NSASM_OK) clear_error();
     return st;
 }
 
 nsasm_status update_entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, double dt,
                           const void *u, const void *p, const uint8_t *mask, void *rhs, void *u_new, void *stream) {
+    const hipEvent_t ph = take_phase_event();  // consumed by this call, whatever its outcome
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
     if (params->flags != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "flags must be 0 for the explicit update");
@@ -982,8 +991,8 @@ nsasm_status update_entry(const nsasm_mesh *m, const nsasm_params *params, nsasm
                 (mask && overlaps(rhs, vec, mask, mb))))
         return fail(NSASM_ERR_INVALID_ARGUMENT, "rhs overlaps another argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const nsasm_status st = (prec == NSASM_FP64) ? run_update<double>(m, *params, dt, u, p, mask, rhs, u_new, s)
-                                                 : run_update<float>(m, *params, dt, u, p, mask, rhs, u_new, s);
+    const nsasm_status st = (prec == NSASM_FP64) ? run_update<double>(m, *params, dt, u, p, mask, rhs, u_new, ph, s)
+                                                 : run_update<float>(m, *params, dt, u, p, mask, rhs, u_new, ph, s);
     if (st == NSASM_OK) clear_error();
     return st;
 }
@@ -997,7 +1006,7 @@ nsasm_status compute_lumped_volume(nsasm_mesh *m, hipStream_t s) {
     if (m->scatter != NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(fill_zero(m->lumped, m->n_nodes, s));
     const KParams<double> kp{};
     const NodeFields<double> F{nullptr, nullptr, nullptr};
-    return launch<double, kNoEddy, kAdvective, kMass>(m, kp, F, m->lumped, false, nullptr, s);
+    return launch<double, kNoEddy, kAdvective, kMass>(m, kp, F, m->lumped, false, nullptr, nullptr, s);
 }
 
 }  // namespace nsasm

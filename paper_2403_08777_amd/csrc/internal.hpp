@@ -16,6 +16,10 @@ namespace nsasm {
 nsasm_status fail(nsasm_status status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 
+// The event set by nsasm_set_phase_event on this thread (or null), which the
+// caller then owns; the pending event is cleared.
+hipEvent_t take_phase_event();
+
 // Map a HIP error to NSASM_ERR_DEVICE (or OUT_OF_MEMORY) with context.
 nsasm_status hip_fail(hipError_t err, const char *what);
 
@@ -139,6 +143,31 @@ __device__ inline uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *lds4, 
     __syncthreads();
     *total = all;
     return before + x - v;
+}
+
+// Rows of adj(J) for J = [d_1 | d_2 | d_3], d_k = x_k - x_0: c_1 = d_2 x d_3,
+// c_2 = d_3 x d_1, c_3 = d_1 x d_2; returns det J = d_1 . c_1.  The assembly
+// kernels and the mesh validation both call this, so the determinant a mesh
+// is validated with is the one the kernels invert.
+__device__ inline double tet_adjugate(const double (&xe)[4][3], double (&c1)[3], double (&c2)[3],
+                                      double (&c3)[3], double (&d1)[3]) {
+    double d2[3], d3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        d1[i] = xe[1][i] - xe[0][i];
+        d2[i] = xe[2][i] - xe[0][i];
+        d3[i] = xe[3][i] - xe[0][i];
+    }
+    c1[0] = d2[1] * d3[2] - d2[2] * d3[1];
+    c1[1] = d2[2] * d3[0] - d2[0] * d3[2];
+    c1[2] = d2[0] * d3[1] - d2[1] * d3[0];
+    c2[0] = d3[1] * d1[2] - d3[2] * d1[1];
+    c2[1] = d3[2] * d1[0] - d3[0] * d1[2];
+    c2[2] = d3[0] * d1[1] - d3[1] * d1[0];
+    c3[0] = d1[1] * d2[2] - d1[2] * d2[1];
+    c3[1] = d1[2] * d2[0] - d1[0] * d2[2];
+    c3[2] = d1[0] * d2[1] - d1[1] * d2[0];
+    return d1[0] * c1[0] + d1[1] * c1[1] + d1[2] * c1[2];
 }
 
 // Workgroup b runs on XCD (b mod 8).  Give each XCD one contiguous run of

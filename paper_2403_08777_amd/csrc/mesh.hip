@@ -13,6 +13,7 @@
 //      the ascending list of its distinct nodes and one-byte local ids per
 //      element, so a workgroup can stage the patch's nodes through LDS.
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <new>
 #include <vector>
@@ -25,6 +26,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr uint32_t kBadRange = 1u, kBadRepeat = 2u, kBadDet = 4u;
 constexpr int kBboxBlocks = 512;
+constexpr double kDetRelTol = 64.0 * DBL_EPSILON;
 
 struct CreateFlags {
     uint32_t bits;
@@ -114,7 +116,7 @@ __device__ inline uint64_t spread_bits3(uint64_t v) {
     return v;
 }
 
-// Morton key of each element's centroid (63 bits) and the det J == 0 check.
+// Morton key of each element's centroid (63 bits) and the degenerate-element check.
 __global__ __launch_bounds__(kThreads) void k_element_keys(const double *x, const int32_t *conn,
                                                             int64_t ne, const double *box,
                                                             uint64_t *keys, int32_t *vals,
@@ -128,15 +130,19 @@ __global__ __launch_bounds__(kThreads) void k_element_keys(const double *x, cons
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int i = 0; i < 3; ++i) xe[a][i] = x[3 * static_cast<int64_t>(ids[a]) + i];
-    double d[3][3];
+    // The determinant the assembly kernels invert, rejected when it is not a
+    // normal number or is within rounding of zero: below 64 eps |d_1||d_2||d_3|
+    // (Hadamard's bound is |d_1||d_2||d_3|) the kernels' sign and value of
+    // det J would be rounding noise, and 1/det could overflow.
+    double c1[3], c2[3], c3[3], d1[3];
+    const double det = tet_adjugate(xe, c1, c2, c3, d1);
+    double len2[3] = {0.0, 0.0, 0.0};  // squared edge lengths |d_k|^2
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) d[k][i] = xe[k + 1][i] - xe[0][i];
-    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
-                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
-                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
-    if (det == 0.0 || !isfinite(det)) {
+        for (int i = 0; i < 3; ++i) len2[k] += (xe[k + 1][i] - xe[0][i]) * (xe[k + 1][i] - xe[0][i]);
+    const double bound = kDetRelTol * sqrt(len2[0]) * sqrt(len2[1]) * sqrt(len2[2]);
+    if (!isfinite(det) || !(fabs(det) >= DBL_MIN) || !(fabs(det) > bound)) {
         atomicOr(&flags->bits, kBadDet);
         atomicMin(&flags->first_bad, static_cast<int32_t>(e));
     }
@@ -684,7 +690,9 @@ nsasm_status create(const double *coords, int64_t nn, const int32_t *conn, int64
     NSASM_TRY(check_launch("k_element_keys"));
     NSASM_TRY(read_flags(d_flags, stream, &h));
     if (h.bits & kBadDet)
-        return fail(NSASM_ERR_DEGENERATE_ELEMENT, "element %d has det J == 0 or a non-finite vertex",
+        return fail(NSASM_ERR_DEGENERATE_ELEMENT,
+                    "element %d has det J within rounding of zero (|det J| <= 64 eps |d1||d2||d3|), "
+                    "a subnormal det J or a non-finite vertex",
                     h.first_bad);
 
     NSASM_TRY(device_alloc(&m->perm, static_cast<size_t>(nn), "node permutation"));

@@ -10,6 +10,7 @@ namespace nsasm {
 
 namespace {
 thread_local std::string g_message;
+thread_local hipEvent_t g_phase_event = nullptr;
 std::atomic<long> g_alloc_count{0};
 
 long fail_alloc_at() {
@@ -32,6 +33,12 @@ nsasm_status fail(nsasm_status status, const char *fmt, ...) {
 }
 
 void clear_error() { g_message.clear(); }
+
+hipEvent_t take_phase_event() {
+    hipEvent_t e = g_phase_event;
+    g_phase_event = nullptr;
+    return e;
+}
 
 nsasm_status hip_fail(hipError_t err, const char *what) {
     nsasm_status s = (err == hipErrorOutOfMemory || err == hipErrorMemoryAllocation)
@@ -80,4 +87,10 @@ void device_free(void *p) {
 
 extern "C" const char *nsasm_last_error(void) { return nsasm::g_message.c_str(); }
 
-extern "C" const char *nsasm_version(void) { return "0.1.0"; }
+extern "C" nsasm_status nsasm_set_phase_event(void *event) {
+    nsasm::g_phase_event = static_cast<hipEvent_t>(event);
+    nsasm::clear_error();
+    return NSASM_OK;
+}
+
+extern "C" const char *nsasm_version(void) { return "0.2.0"; }

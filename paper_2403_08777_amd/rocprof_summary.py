@@ -1,21 +1,18 @@
 """Turn rocprofv3 output into the short text summaries kept under profiles/.
 
     python -m paper_2403_08777_amd.rocprof_summary stats KERNEL_STATS_CSV --command CMD
-    python -m paper_2403_08777_amd.rocprof_summary traffic --fetch F --write W \\
-        --workload NAME --command-fetch CMD --command-write CMD
-    python -m paper_2403_08777_amd.rocprof_summary counters PMC_CSV [PMC_CSV ...] --trace STATS_CSV \\
-        --command CMD --trace-command CMD [--json-out FILE]
+    python -m paper_2403_08777_amd.rocprof_summary counters PASS_A.csv PASS_B.csv ... \\
+        --workload NAME --title TEXT --command CMD_A --command CMD_B ... \\
+        [--trace STATS_CSV --trace-command CMD] --json-out profiles/counters_NAME.json
 
 ``stats`` prints a markdown table of per-kernel call counts and durations from
-a ``--kernel-trace --stats -f csv`` run.  ``traffic`` reads two ``--pmc`` runs
-(FETCH_SIZE, then WRITE_SIZE; CSV or rocpd database), scales each counter by
-what it reads for the plain 1 GiB device copy that ``bench.py
---copy-calibration`` performs, and prints a JSON record of the HBM bytes per
-assembly call (forward, VJP) tagged with a digest of the HIP sources, which
-``bench.py`` uses only while the kernels are unchanged.  ``counters`` reads one
-``--pmc`` run of SQ instruction counters (and the kernel-trace statistics of
-the same workload for durations) and prints per-wave instruction counts and an
-estimate of how busy the vector ALUs were.
+a ``--kernel-trace --stats -f csv`` run.  ``counters`` reads several ``--pmc``
+passes over one workload (each run with ``bench.py --copy-calibration``, whose
+plain 1 GiB device copy calibrates FETCH_SIZE and WRITE_SIZE), prints a
+markdown table per kernel and writes the JSON record ``bench.py`` reads: HBM
+bytes, executed FP64/FP32 flops, per-wave instruction and LDS counters and the
+L2 hit rate of every assembly kernel, tagged with a digest of the HIP sources
+so that it is used only while the kernels are unchanged.
 """
 
 from __future__ import annotations
@@ -81,38 +78,6 @@ def copy_scale(rows, counter):
     return COPY_BYTES / (kib * 1024.0), kib
 
 
-def traffic(args):
-    f_rows, w_rows = read_counters(args.fetch), read_counters(args.write)
-    fetch, write = median_by_kernel(f_rows, "FETCH_SIZE"), median_by_kernel(w_rows, "WRITE_SIZE")
-    fs, fkib = copy_scale(f_rows, "FETCH_SIZE")
-    ws, wkib = copy_scale(w_rows, "WRITE_SIZE")
-    calls = {}
-
-    def targs(name):
-        m = re.match(r"(\w+)<(.*)>$", name)
-        return (m.group(1), [a.strip() for a in m.group(2).split(",")]) if m else (name, [])
-
-    # the benchmark's calls: k_assemble_patch<double, EDDY none, CONV advective,
-    # MODE, GATHER> followed by k_gather_partials<double, 3>
-    for mode, tag in (("fwd", "0"), ("vjp", "1")):
-        parts = [key for key in fetch if targs(key[0]) == ("k_assemble_patch", ["double", "0", "0", tag, "true"])]
-        gathers = [key for key in fetch if targs(key[0]) == ("k_gather_partials", ["double", "3"])]
-        keys = parts + gathers
-        if not parts:
-            continue
-        fb = sum(fetch[k] for k in keys) * 1024.0 * fs
-        wb = sum(write.get(k, 0.0) for k in keys) * 1024.0 * ws
-        calls[mode] = {"kernels": [f"{k[0]} (grid {k[1]})" for k in keys], "fetch_bytes": fb,
-                       "write_bytes": wb, "bytes": fb + wb}
-    rec = {"workload": args.workload, "scatter": args.scatter, "source_sha256": source_digest(),
-           "command_fetch": args.command_fetch, "command_write": args.command_write,
-           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": fkib, "write_kib": wkib,
-                                "fetch_scale": fs, "write_scale": ws},
-           "calls": calls}
-    json.dump(rec, sys.stdout, indent=1)
-    print()
-
-
 def stats(args):
     with open(args.csv) as f:
         rows = list(csv.DictReader(f))
@@ -136,83 +101,101 @@ def stats(args):
 SIMDS = 256 * 4        # MI355X: 256 compute units, 4 SIMDs each
 CLOCK_HZ = 2.4e9       # peak engine clock
 VALU_CYCLES = 4        # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+FLOP_COUNTERS = {p: [f"SQ_INSTS_VALU_{op}_{p}" for op in ("ADD", "MUL", "FMA", "TRANS")] for p in ("F64", "F32")}
 
 
 def counters(args):
-    rows = [r for path in args.pmc for r in read_counters(path)]
+    """One record per workload from several --pmc passes over the same short
+    bench run (each with --copy-calibration): per kernel the median
+    per-dispatch value of every counter, HBM bytes from FETCH_SIZE and
+    WRITE_SIZE scaled by what each counter reads for the 1 GiB device copy of
+    its own pass, executed flops from the VALU type counters, the L2 hit rate,
+    plus a markdown table with the VALU-busy estimate from the kernel-trace
+    durations."""
+    per_pass = [read_counters(path) for path in args.pmc]
+    rows = [r for rs in per_pass for r in rs]
     names = sorted({c for _, _, c, _ in rows})
     med = {c: median_by_kernel(rows, c) for c in names}
-    dur = {}
-    with open(args.trace) as f:
-        for r in csv.DictReader(f):
-            dur[short_name(r["Name"])] = float(r["AverageNs"]) * 1e-9
+    scale = {}
+    for rs in per_pass:
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            if any(c == ctr for _, _, c, _ in rs):
+                scale[ctr] = copy_scale(rs, ctr)
     pat = re.compile(args.kernels)
-    keys = sorted(k for k in med.get("SQ_WAVES", {}) if pat.search(k[0]))
-    shown = [c for c in names if c != "SQ_WAVES"]
-    # executed floating-point operations: a wave instruction is 64 lane
-    # operations, an FMA two flops
-    flop_sets = {p: [f"SQ_INSTS_VALU_{op}_{p}" for op in ("ADD", "MUL", "FMA", "TRANS")] for p in ("F64", "F32")}
-    have = {p: [c for c in cs if c in med] for p, cs in flop_sets.items()}
+    # one grid per kernel: the workload's (the one dispatched most often)
+    count = defaultdict(int)
+    for k, g, c, _ in rows:
+        if c == "SQ_WAVES":
+            count[(short_name(k), g)] += 1
+    best = {}
+    for (k, g), n in count.items():
+        if pat.search(k) and (k not in best or n > count[(k, best[k])]):
+            best[k] = g
+    dur = {}
+    if args.trace:
+        with open(args.trace) as f:
+            for r in csv.DictReader(f):
+                dur[short_name(r["Name"])] = float(r["AverageNs"]) * 1e-9
+    have = {p: [c for c in cs if c in med] for p, cs in FLOP_COUNTERS.items()}
 
     def flops(key, prec):
         return 64.0 * sum(med[c].get(key, 0.0) * (2.0 if "_FMA_" in c else 1.0) for c in have[prec])
-    print(f"Commands: `{args.command}`\n")
-    print(f"Durations: `{args.trace_command}`\n")
-    print("Per-wave medians over the dispatches of each kernel (a wave is 64 elements in the element "
-          "phase). VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x average duration), an "
-          "estimate of the share of SIMD cycles spent issuing vector instructions: 4 cycles is what a "
-          "wave64 FP64 FMA takes on a 16-lane SIMD (instructions that issue faster make it an "
-          "overestimate) and 2.4 GHz is the peak clock (a lower clock makes it an underestimate).\n")
-    if have["F64"] or have["F32"]:
-        print("Executed flops per grid item (an element, or a node for the gather) = 64 lanes x "
-              "(ADD + MUL + 2 FMA + TRANS instructions) / grid size, counting every lane of a wave "
-              "instruction.\n")
-    extra = [p for p in ("F64", "F32") if have[p]]
-    lds_ratio = "SQ_LDS_BANK_CONFLICT" in med and "SQ_LDS_IDX_ACTIVE" in med
+
     l2 = next(((h, m) for h, m in (("TCC_HIT_sum", "TCC_MISS_sum"), ("TCC_HIT", "TCC_MISS"))
                if h in med and m in med), None)
-    if l2:
-        print("L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS) over the kernel's L2 requests.\n")
-    if lds_ratio:
-        print("Conflict share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE: the fraction of the LDS's "
-              "indexed-active cycles spent stalled on bank conflicts (a ratio of two counters that "
-              "aggregate the same way).\n")
+    shown = [c for c in names if c not in ("SQ_WAVES", "FETCH_SIZE", "WRITE_SIZE") and not c.startswith("TCC_")]
+    rec = {"workload": args.workload, "source_sha256": source_digest(), "commands": args.command,
+           "trace_command": args.trace_command,
+           "copy_calibration": {ctr: {"copy_bytes": COPY_BYTES, "counter_kib": kib, "bytes_per_kib": sc * 1024.0}
+                                for ctr, (sc, kib) in scale.items()},
+           "kernels": {}}
+    print(f"# Counters: {args.title}\n")
+    print("Commands (run from the repository root on one MI355X, one `--pmc` pass each):\n")
+    for c in args.command:
+        print(f"- `{c}`")
+    if args.trace_command:
+        print(f"\nDurations: `{args.trace_command}`\n")
+    print("\nPer-dispatch medians per kernel; per-wave counts divide by SQ_WAVES (a wave is 64 elements in "
+          "the element phase, 64 nodes in the gather). HBM bytes = FETCH_SIZE and WRITE_SIZE, each scaled by "
+          "what it reads for a plain 1 GiB device copy in the same pass. Executed flops = 64 lanes x (ADD + "
+          "MUL + 2 FMA + TRANS) VALU instructions of the type. VALU busy = SQ_INSTS_VALU x 4 cycles / "
+          "(1024 SIMDs x 2.4 GHz x average duration). Conflict share = SQ_LDS_BANK_CONFLICT / "
+          "SQ_LDS_IDX_ACTIVE. L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS).\n")
     print("| kernel | grid | waves | " + " | ".join(c.replace("SQ_", "") + "/wave" for c in shown) +
-          "".join(f" | {p} flop/item" for p in extra) + (" | conflict share" if lds_ratio else "") +
-          (" | L2 hit rate" if l2 else "") + " | avg us | VALU busy |")
-    print("|---|---:|---:|" + "---:|" * (len(shown) + len(extra) + int(lds_ratio) + int(bool(l2))) + "---:|---:|")
-    rec = {"source_sha256": source_digest(), "command": args.command, "kernels": {}}
-    for key in keys:
-        waves = med["SQ_WAVES"][key]
-        vals = " | ".join(f"{med[c].get(key, float('nan')) / waves:.1f}" for c in shown)
-        fl = "".join(f" | {flops(key, p) / key[1]:.1f}" for p in extra)
-        if lds_ratio:
-            act = med["SQ_LDS_IDX_ACTIVE"].get(key, 0.0)
-            fl += f" | {med['SQ_LDS_BANK_CONFLICT'].get(key, 0.0) / act:.2f}" if act else " | -"
+          " | HBM MB | F64 flop/item | F32 flop/item | conflict share | L2 hit | avg us | VALU busy |")
+    print("|---|---:|---:|" + "---:|" * len(shown) + "---:|---:|---:|---:|---:|---:|---:|")
+    for kname, grid in sorted(best.items()):
+        key = (kname, grid)
+        waves = med["SQ_WAVES"].get(key, 0.0)
+        if not waves:
+            continue
+        pw = {c: med[c][key] / waves for c in shown if key in med[c]}
+        ent = {"grid": grid, "waves": waves, "per_wave": pw}
+        hb = 0.0
+        for ctr, name in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
+            if ctr in med and key in med[ctr] and ctr in scale:
+                ent[name] = med[ctr][key] * 1024.0 * scale[ctr][0]
+                hb += ent[name]
+        ent["hbm_bytes"] = hb if ("fetch_bytes" in ent and "write_bytes" in ent) else None
+        if have["F64"] or have["F32"]:
+            ent["f64_flops"], ent["f32_flops"] = flops(key, "F64"), flops(key, "F32")
         if l2:
             hit, miss = med[l2[0]].get(key, 0.0), med[l2[1]].get(key, 0.0)
-            fl += f" | {hit / (hit + miss):.2f}" if hit + miss else " | -"
-        d = dur.get(key[0])
-        busy = (med["SQ_INSTS_VALU"][key] * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
-                if d and "SQ_INSTS_VALU" in med else float("nan"))
-        print(f"| `{key[0]}` | {key[1]} | {waves:.0f} | {vals}{fl} | "
-              f"{d * 1e6 if d else float('nan'):.1f} | {busy:.2f} |")
-        rec["kernels"][f"{key[0]} (grid {key[1]})"] = {
-            "waves": waves, "per_wave": {c: med[c].get(key) / waves for c in shown if key in med[c]},
-            **{f"{p.lower()}_flops": flops(key, p) for p in extra}}
-    if args.json_out:
-        # per benchmark call: the patch kernel of the mode plus its gather
-        calls = {}
-        for mode, tag in (("fwd", "0"), ("vjp", "1")):
-            ks = [k for k in keys if k[0] in (f"k_assemble_patch<double, 0, 0, {tag}, true>",
-                                              "k_gather_partials<double, 3>")]
-            if len(ks) == 2 and have["F64"]:
-                calls[mode] = {"kernels": [f"{k[0]} (grid {k[1]})" for k in ks],
-                               "fp64_flops": sum(flops(k, "F64") for k in ks)}
-        rec["calls"] = calls
-        with open(args.json_out, "w") as f:
-            json.dump(rec, f, indent=1)
-            f.write("\n")
+            ent["l2_hit_rate"] = hit / (hit + miss) if hit + miss else None
+        rec["kernels"][kname] = ent
+        d = dur.get(kname)
+        busy = (pw["SQ_INSTS_VALU"] * waves * VALU_CYCLES / (SIMDS * CLOCK_HZ * d)
+                if d and "SQ_INSTS_VALU" in pw else float("nan"))
+        act = pw.get("SQ_LDS_IDX_ACTIVE")
+        share = f"{pw.get('SQ_LDS_BANK_CONFLICT', 0.0) / act:.2f}" if act else "-"
+        l2s = f"{ent['l2_hit_rate']:.2f}" if ent.get("l2_hit_rate") is not None else "-"
+        hbs = f"{ent['hbm_bytes'] / 1e6:.1f}" if ent.get("hbm_bytes") else "-"
+        print(f"| `{kname}` | {grid} | {waves:.0f} | " + " | ".join(f"{pw.get(c, float('nan')):.1f}" for c in shown)
+              + f" | {hbs} | {ent.get('f64_flops', 0.0) / grid:.1f} | {ent.get('f32_flops', 0.0) / grid:.1f} | "
+              f"{share} | {l2s} | {d * 1e6 if d else float('nan'):.1f} | {busy:.2f} |")
+    with open(args.json_out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
 
 
 def main():
@@ -223,23 +206,17 @@ def main():
     s.add_argument("--command", required=True)
     s.add_argument("--top", type=int, default=25)
     s.add_argument("--dispatches", help="kernel_trace.csv of the same run, for LDS and scratch columns")
-    t = sub.add_parser("traffic")
-    t.add_argument("--fetch", required=True)
-    t.add_argument("--write", required=True)
-    t.add_argument("--workload", required=True)
-    t.add_argument("--scatter", default="patch_gather")
-    t.add_argument("--command-fetch", required=True)
-    t.add_argument("--command-write", required=True)
     c = sub.add_parser("counters")
-    c.add_argument("pmc", nargs="+", help="counter CSVs of one or more --pmc passes over the same workload")
-    c.add_argument("--trace", required=True, help="kernel_stats.csv of a --kernel-trace --stats run")
-    c.add_argument("--command", required=True)
-    c.add_argument("--trace-command", required=True)
-    c.add_argument("--kernels", default=r"k_assemble_patch<\w+, 0, 0, [01], true>|k_gather_partials")
-    c.add_argument("--json-out", help="also write the per-kernel figures and the FP64 flops of the "
-                                      "benchmark calls as a JSON record tagged with the source digest")
+    c.add_argument("pmc", nargs="+", help="counter CSVs (or rocpd databases) of --pmc passes over one workload")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", required=True, help="the command of each pass, in order")
+    c.add_argument("--trace", help="kernel_stats.csv of a --kernel-trace --stats run of the same workload")
+    c.add_argument("--trace-command", default="")
+    c.add_argument("--kernels", default=r"^k_assemble_patch<|^k_gather_partials<")
+    c.add_argument("--json-out", required=True, help="the JSON record bench.py reads (counters_<workload>.json)")
     args = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "counters": counters}[args.cmd](args)
+    {"stats": stats, "counters": counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

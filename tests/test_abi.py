@@ -104,7 +104,7 @@ def test_host_side_argument_checks():
     assert lib.nsasm_stream_scale(None, None, 0, 2.0, None) == 0
     assert lib.nsasm_stream_scale(None, None, 5, 2.0, None) == 1 and b"a is NULL" in lib.nsasm_last_error()
     assert lib.nsasm_mesh_destroy(None) == 0
-    assert api.version() == "0.1.0"
+    assert api.version() == "0.2.0"
 
 
 def test_error_class():

@@ -2,6 +2,8 @@
 the oracle's complex-step dense Jacobian, and torch.autograd.gradcheck through
 the autograd.Function."""
 
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -148,3 +150,59 @@ def test_autograd_pressure_and_forward_mode():
     (api.NSAssembleRHS.apply(u, pp, pr.mesh, prm) * lam).sum().backward()
     gp = api.assemble_rhs_vjp_p(pr.mesh, lam, prm)
     assert oracle.rel_l2(pp.grad.cpu().numpy(), gp.cpu().numpy()) <= 1e-15
+
+
+def test_double_backward_raises():
+    """The VJP kernels are not themselves differentiated: a second-order
+    derivative through NSAssembleRHS.backward raises instead of returning a
+    result that silently drops terms."""
+    from paper_2403_08777_amd import api
+
+    case = Case(3, jitter=True, permute=True, mu=1e-3, cs=0.1)
+    pr = Prepared(case)
+    u, p, lam = pr.fields(torch.float64)
+    uu = u.clone().requires_grad_(True)
+    rhs = api.NSAssembleRHS.apply(uu, p, pr.mesh, case.params())
+    (g,) = torch.autograd.grad((rhs * lam).sum(), uu, create_graph=True)
+    ref = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
+    assert torch.equal(g.detach(), ref)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(g.sum(), uu)
+
+
+def test_phase_event_splits_the_call():
+    """nsasm_set_phase_event: the next call records the event between its
+    element kernel and its gather kernel, so start <= phase <= end with both
+    parts taking time; the call's result is unchanged, and the event is
+    consumed (a later call leaves it where it was)."""
+    from paper_2403_08777_amd import api
+
+    case = Case(16, jitter=True, permute=True, mu=1e-3)
+    pr = Prepared(case)
+    u, p, lam = pr.fields(torch.float64)
+    ref = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
+    e0, ph, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    ph.record()
+    torch.cuda.synchronize()
+    e0.record()
+    api.set_phase_event(ph)
+    got = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
+    e1.record()
+    torch.cuda.synchronize()
+    a, b = e0.elapsed_time(ph), ph.elapsed_time(e1)
+    log(f"phase split: element kernel {a * 1e3:.1f} us, gather {b * 1e3:.1f} us")
+    assert a > 0 and b > 0
+    assert torch.equal(got, ref)
+    # consumed: another call does not move the event
+    api.assemble_rhs(pr.mesh, u, p, case.params())
+    torch.cuda.synchronize()
+    assert abs(e0.elapsed_time(ph) - a) < 1e-9
+    # a failing call consumes it too (NULL output pointer: rejected on the host)
+    api.set_phase_event(ph)
+    prm = case.params().c_struct()
+    assert api.lib.nsasm_assemble_rhs(pr.mesh.handle, ctypes.byref(prm), 0, u.data_ptr(), p.data_ptr(), None,
+                                      None) == 1
+    api.assemble_rhs(pr.mesh, u, p, case.params())
+    torch.cuda.synchronize()
+    assert abs(e0.elapsed_time(ph) - a) < 1e-9
+    api.set_phase_event(None)

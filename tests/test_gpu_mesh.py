@@ -214,3 +214,42 @@ def test_injected_allocation_failure(k):
     log(out.stdout + out.stderr[-2000:])
     assert out.returncode == 0
     assert "STATUS OUT_OF_MEMORY" in out.stdout and "OK " in out.stdout
+
+
+def test_rounding_level_sliver_rejected():
+    """Four vertices coplanar up to the rounding of their coordinates (exact
+    determinant non-zero but ~1e-16 of |d1||d2||d3|; tests/test_sliver.py pins
+    the fixture) are refused as DEGENERATE_ELEMENT, alone and inside a mesh; a
+    thin but sound element (1e-6 of the bound's scale) is accepted and matches
+    the oracle."""
+    from paper_2403_08777_amd import api
+    from tests.test_sliver import sliver_coords, thin_coords
+
+    conn1 = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    log("sliver alone")
+    with pytest.raises(api.NsasmError) as ei:
+        _mesh(sliver_coords(), conn1)
+    assert ei.value.status_name == "DEGENERATE_ELEMENT" and "element 0" in str(ei.value)
+    # inside a cube mesh: the sliver's vertices appended as four extra nodes
+    m = synth.cube_mesh(3, jitter=True)
+    coords = np.vstack([m.coords, sliver_coords()])
+    nn = m.n_nodes
+    conn = np.vstack([m.conn, np.array([[nn, nn + 1, nn + 2, nn + 3]], dtype=np.int32)])
+    log("sliver in a mesh")
+    with pytest.raises(api.NsasmError) as ei:
+        _mesh(coords, conn)
+    assert ei.value.status_name == "DEGENERATE_ELEMENT" and f"element {m.n_elems}" in str(ei.value)
+    log("thin element")
+    xe = thin_coords()
+    mesh = _mesh(xe, conn1)
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(5)
+    u, p = rng.standard_normal((4, 3)), rng.standard_normal(4)
+    P = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    ut = mesh.to_mesh_order(torch.from_numpy(u).to(dev))
+    pt = mesh.to_mesh_order(torch.from_numpy(p).to(dev))
+    r = mesh.from_mesh_order(api.assemble_rhs(mesh, ut, pt, P)).cpu().numpy()
+    ref = oracle.rhs(xe, conn1, u, p, oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE))
+    err = oracle.rel_l2(r, ref)
+    log(f"  thin element rel_l2 {err:.2e}")
+    assert np.isfinite(r).all() and err <= 1e-9  # J^-1 has condition ~1e6 here

@@ -371,3 +371,35 @@ def test_high_valence_fan(scatter):
         log(f"  {str(dtype)[6:]}: rhs {er:.2e}, grad {eg:.2e}")
         assert er <= tol and eg <= tol
     mesh.close()
+
+
+def test_anisotropic_elements_vreman_vjp():
+    """The Vreman VJP on the same kind of squashed elements (3^3 jittered cube,
+    z scaled by 1e-4), against the 60-digit reference of tests/hp_vreman.py
+    (exact frozen-viscosity VJP plus Vreman's viscosity differentiated in
+    high-precision decimals): the kernel must be as close to it as the FP64
+    oracle, within a factor of 10; mixed precision within its usual error."""
+    from paper_2403_08777_amd import api, synth
+    from tests import hp_vreman
+
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    coords = m.coords * np.array([1.0, 1.0, 1e-4])
+    u, _ = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    rho, mu, cs = 1.0, 1e-3, 0.1
+    log("anisotropic vreman vjp: building the 60-digit reference on the host")
+    ref = hp_vreman.vjp(coords, m.conn, u, lam, rho, mu, cs, synth.BODY_FORCE)
+    ora = oracle.vjp(coords, m.conn, u, lam, oracle.Params(rho, mu, cs, synth.BODY_FORCE, model="vreman"))
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(m.conn).to(dev))
+    prm = api.Params(rho, mu, cs, synth.BODY_FORCE, "vreman")
+    e_ora = oracle.rel_l2(ora, ref)
+    for dtype in (torch.float64, torch.float32):
+        tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype))
+        got = mesh.from_mesh_order(api.assemble_rhs_vjp(mesh, tm(u), tm(lam), prm)).double().cpu().numpy()
+        e_gpu = oracle.rel_l2(got, ref)
+        log(f"  {dtype}: kernel {e_gpu:.2e}, oracle {e_ora:.2e}")
+        if dtype == torch.float64:
+            assert e_gpu <= max(1e-13, 10 * e_ora)
+        else:
+            assert e_gpu <= TOL_MIXED

@@ -140,3 +140,36 @@ def test_update_argument_checks():
     # a valid call still works afterwards
     assert call(prm, DT, u.data_ptr(), rhs.data_ptr(), out.data_ptr()) == 0
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "patch", "patch_gather"])
+def test_update_unreferenced_nodes(scatter):
+    """Nodes that no element references have V^L = 0: the stage keeps them
+    unchanged (finite, equal to u) in FP64 and mixed precision, and the other
+    nodes match the oracle."""
+    from paper_2403_08777_amd import api
+
+    m = synth.cube_mesh(5, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    extra = 7
+    rng = np.random.default_rng(12)
+    coords = np.vstack([m.coords, rng.uniform(2.0, 3.0, (extra, 3))])
+    u2 = np.vstack([u, rng.uniform(-1.0, 1.0, (extra, 3))])
+    p2 = np.concatenate([p, rng.uniform(-1.0, 1.0, extra)])
+    dev = torch.device("cuda")
+    log(f"update with {extra} unreferenced nodes, {scatter}")
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(m.conn).to(dev), scatter=scatter)
+    case = Case(5, mu=1e-4, cs=0.1)
+    ref, _ = oracle.explicit_update(coords, m.conn, u2, p2, case.oracle_params(), DT)
+    vl = mesh.from_mesh_order(mesh.lumped_volume()).cpu().numpy()
+    assert np.all(vl[-extra:] == 0)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-4)):
+        tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype))
+        un = mesh.from_mesh_order(api.explicit_update(mesh, tm(u2), tm(p2), case.params(), DT)).double()
+        un = un.cpu().numpy()
+        uin = u2.astype(np.float32).astype(np.float64) if dtype == torch.float32 else u2
+        assert np.isfinite(un).all()
+        assert np.array_equal(un[-extra:], uin[-extra:])
+        err = oracle.rel_l2(un[:-extra] - uin[:-extra], ref[:-extra] - u2[:-extra])
+        log(f"  {dtype}: increment rel_l2 {err:.2e}")
+        assert err <= tol

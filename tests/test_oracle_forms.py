@@ -238,3 +238,18 @@ def test_forms_jvp_exact_rational(oracle_lib, form):
     ref = frac_to_np(exact.assemble_jvp(coords, conn, uq, pq, dq, eq, rho, mu, fq, form=form))
     got = oracle.jvp(xf, conn, uf, pf[:, 0], df, ef[:, 0], oracle.Params(1.0, float(mu), 0.0, F, form=form))
     assert oracle.rel_l2(got, ref) < 1e-14
+
+
+def test_vreman_vjp_high_precision_reference(oracle_lib):
+    """The 60-digit Vreman VJP reference (tests/hp_vreman.py: exact frozen-
+    viscosity VJP plus Vreman's viscosity differentiated by central differences
+    in decimals) and the oracle's analytic Vreman VJP agree on a well-shaped
+    jittered mesh, where FP64 rounding is benign: a check of both."""
+    from tests import hp_vreman
+
+    m = synth.cube_mesh(2, jitter=True, permute=True)
+    u, _ = synth.taylor_green(m)
+    lam = synth.adjoint(m.n_nodes)
+    ref = hp_vreman.vjp(m.coords, m.conn, u, lam, 1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    ora = oracle.vjp(m.coords, m.conn, u, lam, oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE, model="vreman"))
+    assert oracle.rel_l2(ora, ref) <= 1e-14

@@ -65,3 +65,23 @@ def test_update_mask_and_linearity(oracle_lib):
     vl = oracle.lumped_volume(m.coords, m.conn)
     inc = (u1 - u) * (prm.rho * vl)[:, None] / 1e-2
     np.testing.assert_allclose(inc[~fixed], R[~fixed], rtol=1e-10, atol=1e-14)
+
+
+def test_update_leaves_unreferenced_nodes_unchanged(oracle_lib):
+    """A node that no element references has V^L = 0 and R = 0: the stage
+    leaves it unchanged (u_new = u, finite) instead of producing 0/0, and the
+    referenced nodes are updated exactly as on the mesh without the extra
+    nodes."""
+    m = synth.cube_mesh(3, jitter=True, permute=True)
+    u, p = synth.taylor_green(m)
+    extra = 5
+    rng = np.random.default_rng(11)
+    coords = np.vstack([m.coords, rng.uniform(2.0, 3.0, (extra, 3))])
+    u2 = np.vstack([u, rng.uniform(-1.0, 1.0, (extra, 3))])
+    p2 = np.concatenate([p, rng.uniform(-1.0, 1.0, extra)])
+    prm = oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    un, R = oracle.explicit_update(coords, m.conn, u2, p2, prm, 1e-2)
+    assert np.isfinite(un).all()
+    assert np.array_equal(un[-extra:], u2[-extra:]) and np.array_equal(R[-extra:], np.zeros((extra, 3)))
+    ref, _ = oracle.explicit_update(m.coords, m.conn, u, p, prm, 1e-2)
+    assert np.array_equal(un[:-extra], ref)
