@@ -238,6 +238,31 @@ nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_params *para
                                 void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, ordering and results as nsasm_assemble_rhs, bit for
+ * bit, but with the gather scatter the per-patch partial sums go to a fixed
+ * 64 MiB region that the library holds on each GPU from its load until the
+ * process ends, not to the mesh's buffer.  No hipMalloc, hipFree, memset or
+ * allocating library routine is called.  (The other scatters use no scratch
+ * memory; for them this is nsasm_assemble_rhs.)
+ * Limit: 3 x (patch node references, nsasm_mesh_info_t.patch_node_refs) x
+ * (8 bytes FP64, 4 bytes MIXED) must not exceed 64 MiB, i.e. about 6 M
+ * tetrahedra in FP64 and 12 M in MIXED on cube-like meshes; larger meshes
+ * are refused with UNSUPPORTED.
+ * Every such call on one GPU uses the same region, whatever the mesh: calls
+ * that overlap in time on one GPU (several streams, several threads) race
+ * and give wrong results.  The region keeps the last call's contents; every
+ * partial sum a call reads was written by that call, so nothing needs
+ * clearing.
+ * Errors: as nsasm_assemble_rhs, plus INVALID_ARGUMENT when the current
+ * device is not the mesh's device and UNSUPPORTED beyond the limit.
+ */
+nsasm_status nsasm_assemble_rhs_noalloc(const nsasm_mesh *mesh, const nsasm_params *params,
+                                        nsasm_precision precision, const void *u, const void *p,
+                                        void *rhs, void *stream);
+
+/*
  * Velocity vector-Jacobian product of the assembled RHS:
  *   grad_u = (d rhs / d u)^T adjoint,
  * the transpose of the linearisation of the Sec. II / V-B operation (the

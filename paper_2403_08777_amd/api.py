@@ -64,6 +64,7 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_to_mesh_order.argtypes = [vp, i32, st, vp, vp, vp]
     lib.nsasm_from_mesh_order.argtypes = [vp, i32, st, vp, vp, vp]
     lib.nsasm_assemble_rhs.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
+    lib.nsasm_assemble_rhs_noalloc.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
     lib.nsasm_assemble_rhs_vjp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp]
     lib.nsasm_assemble_rhs_vjp_p.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp]
     lib.nsasm_assemble_rhs_jvp.argtypes = [vp, ctypes.POINTER(_Params), st, vp, vp, vp, vp, vp]
@@ -74,8 +75,8 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_set_phase_event.argtypes = [vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
-                 "nsasm_assemble_rhs", "nsasm_assemble_rhs_vjp", "nsasm_assemble_rhs_vjp_p",
-                 "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
+                 "nsasm_assemble_rhs", "nsasm_assemble_rhs_noalloc", "nsasm_assemble_rhs_vjp",
+                 "nsasm_assemble_rhs_vjp_p", "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
                  "nsasm_stream_scale", "nsasm_set_phase_event"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
@@ -242,6 +243,22 @@ def assemble_rhs(mesh: Mesh, u: torch.Tensor, p: torch.Tensor, params: Params, o
     prm = params.c_struct(accumulate)
     _check(lib.nsasm_assemble_rhs(mesh.handle, ctypes.byref(prm), prec, u.data_ptr(), p.data_ptr(),
                                   out.data_ptr(), _stream(stream)))
+    return out
+
+
+def assemble_rhs_noalloc(mesh: Mesh, u: torch.Tensor, p: torch.Tensor, params: Params, out: torch.Tensor,
+                        accumulate: bool = False, stream=None) -> torch.Tensor:
+    """As assemble_rhs, through nsasm_assemble_rhs_noalloc: the library
+    allocates nothing (the gather scatter's partial sums use its fixed
+    per-GPU region), so `out` must be given."""
+    prec = _precision_of(u)
+    nn = mesh.n_nodes
+    _dev(u, u.dtype, (nn, 3), "u")
+    _dev(p, u.dtype, (nn,), "p")
+    _dev(out, u.dtype, (nn, 3), "out")
+    prm = params.c_struct(accumulate)
+    _check(lib.nsasm_assemble_rhs_noalloc(mesh.handle, ctypes.byref(prm), prec, u.data_ptr(), p.data_ptr(),
+                                          out.data_ptr(), _stream(stream)))
     return out
 
 

@@ -39,7 +39,9 @@
 //           buffer and a node-parallel kernel adds them in patch order: no
 //           atomics anywhere, bitwise reproducible, no zero-fill.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -828,12 +830,14 @@ nsasm_status record_phase(hipEvent_t phase, hipStream_t s) {
 // With the gather scatter and `up` set, the gather kernel applies the
 // explicit update instead of writing `out`.  `phase` (may be null) is
 // recorded between the element kernel and the gather kernel.
+// `partial` (may be null: the mesh's own buffer) receives the per-patch node
+// sums of the gather scatter.
 template <typename T, int EDDY, int CONV, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, T *out, bool accumulate,
-                    const Update<T> *up, hipEvent_t phase, hipStream_t s) {
+                    const Update<T> *up, hipEvent_t phase, hipStream_t s, T *partial = nullptr) {
     constexpr int NOUT = Fields<MODE>::NOUT;
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
-        T *partial = reinterpret_cast<T *>(m->partial);
+        if (!partial) partial = reinterpret_cast<T *>(m->partial);
         k_assemble_patch<T, EDDY, CONV, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
             m->n_elems, m->n_patches, m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
             m->elem_loc, m->x, F, kp, partial);
@@ -868,26 +872,28 @@ nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, 
 
 template <typename T, int CONV, int MODE>
 nsasm_status launch_eddy(const nsasm_mesh *m, const nsasm_params &p, const KParams<T> &kp, NodeFields<T> F, T *o,
-                         const Update<T> *up, hipEvent_t ph, hipStream_t s) {
+                         const Update<T> *up, hipEvent_t ph, hipStream_t s, T *partial) {
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
-        return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
-    if (p.smagorinsky_cs > 0.0) return launch<T, kSmagorinsky, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
-    return launch<T, kNoEddy, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s);
+        return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s, partial);
+    if (p.smagorinsky_cs > 0.0)
+        return launch<T, kSmagorinsky, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s, partial);
+    return launch<T, kNoEddy, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s, partial);
 }
 
 // Physics selection (convective form, eddy viscosity) of a launch.
 template <typename T, int MODE>
 nsasm_status dispatch(const nsasm_mesh *m, const nsasm_params &p, NodeFields<T> F, T *o, const Update<T> *up,
-                      hipEvent_t ph, hipStream_t s) {
+                      hipEvent_t ph, hipStream_t s, T *partial = nullptr) {
     const KParams<T> kp = kernel_params<T>(p);
     if constexpr (MODE == kVjpP) {
         // the pressure term depends on neither the viscosity nor the convective form
-        return launch<T, kNoEddy, kAdvective, MODE>(m, kp, F, o, (p.flags & NSASM_ACCUMULATE) != 0, up, ph, s);
+        return launch<T, kNoEddy, kAdvective, MODE>(m, kp, F, o, (p.flags & NSASM_ACCUMULATE) != 0, up, ph, s,
+                                                    partial);
     } else {
         if (p.convective_form != NSASM_CONVECTIVE_ADVECTIVE)
-            return launch_eddy<T, kGeneral, MODE>(m, p, kp, F, o, up, ph, s);
-        return launch_eddy<T, kAdvective, MODE>(m, p, kp, F, o, up, ph, s);
+            return launch_eddy<T, kGeneral, MODE>(m, p, kp, F, o, up, ph, s, partial);
+        return launch_eddy<T, kAdvective, MODE>(m, p, kp, F, o, up, ph, s, partial);
     }
 }
 
@@ -901,14 +907,51 @@ nsasm_status fill_zero(T *o, int64_t n, hipStream_t s) {
 
 template <typename T, int MODE>
 nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *fa, const void *fb, const void *fc,
-                 void *out, hipEvent_t ph, hipStream_t s) {
+                 void *out, hipEvent_t ph, hipStream_t s, void *partial) {
     T *o = static_cast<T *>(out);
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     // the gather kernel writes every node, so it needs no zero-fill
     if (!accumulate && m->scatter != NSASM_SCATTER_PATCH_GATHER)
         NSASM_TRY(fill_zero(o, Fields<MODE>::NOUT * m->n_nodes, s));
     const NodeFields<T> F{static_cast<const T *>(fa), static_cast<const T *>(fb), static_cast<const T *>(fc)};
-    return dispatch<T, MODE>(m, p, F, o, nullptr, ph, s);
+    return dispatch<T, MODE>(m, p, F, o, nullptr, ph, s, static_cast<T *>(partial));
+}
+
+// ------------------------------------------------ allocation-free variant
+// The partial sums of nsasm_assemble_rhs_noalloc live in this fixed region
+// rather than in the mesh's buffer.  Each GPU holds its own copy from the
+// library's module load until the process ends.  In host code `scratch` is
+// only a host-side handle of the symbol: its device address on the current
+// GPU comes from hipGetSymbolAddress and is what the kernels receive.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, resolved once per
+// device (with that device current) and kept.
+nsasm_status scratch_address(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(NSASM_ERR_UNSUPPORTED, "device %d is beyond the %d devices the library tracks", device,
+                    kMaxDevices);
+    void *p = g_scratch_ptr[device].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        p = g_scratch_ptr[device].load(std::memory_order_relaxed);
+        if (!p) {
+            hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (err != hipSuccess || !p) {
+                (void)hipGetLastError();
+                return fail(NSASM_ERR_DEVICE, "hipGetSymbolAddress of the scratch region failed: %s",
+                            hipGetErrorString(err));
+            }
+            g_scratch_ptr[device].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return NSASM_OK;
 }
 
 // Forward assembly and the explicit update: fused into the gather kernel with
@@ -937,9 +980,11 @@ struct Arg {
     bool nullable;
 };
 
+// With `no_alloc` the gather scatter's partial sums go to the static scratch
+// region instead of the mesh's buffer.
 template <int MODE>
 nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, Arg a, Arg b, Arg c,
-                   Arg out, void *stream) {
+                   Arg out, void *stream, bool no_alloc = false) {
     const hipEvent_t ph = take_phase_event();  // consumed by this call, whatever its outcome
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
@@ -955,10 +1000,25 @@ nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precis
         if (overlaps(out.ptr, out_bytes, in.ptr, static_cast<size_t>(in.ncomp) * m->n_nodes * es))
             return fail(NSASM_ERR_INVALID_ARGUMENT, "%s overlaps %s", out.name, in.name);
     }
+    void *partial = nullptr;
+    if (no_alloc && m->scatter == NSASM_SCATTER_PATCH_GATHER) {
+        int dev = 0;
+        NSASM_HIP(hipGetDevice(&dev));
+        if (dev != m->device)
+            return fail(NSASM_ERR_INVALID_ARGUMENT, "the current device (%d) is not the mesh's device (%d)", dev,
+                        m->device);
+        const size_t need = static_cast<size_t>(Fields<MODE>::NOUT) * static_cast<size_t>(m->patch_node_refs) * es;
+        if (need > kScratchBytes)
+            return fail(NSASM_ERR_UNSUPPORTED,
+                        "the mesh needs %zu bytes of partial sums; the allocation-free call holds at most %zu",
+                        need, kScratchBytes);
+        NSASM_TRY(scratch_address(dev, &partial));
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *o = const_cast<void *>(out.ptr);
-    const nsasm_status st = (prec == NSASM_FP64) ? run<double, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s)
-                                                 : run<float, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s);
+    const nsasm_status st = (prec == NSASM_FP64)
+                                ? run<double, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s, partial)
+                                : run<float, MODE>(m, *params, a.ptr, b.ptr, c.ptr, o, ph, s, partial);
     if (st == NSASM_OK) clear_error();
     return st;
 }
@@ -1017,6 +1077,14 @@ extern "C" nsasm_status nsasm_assemble_rhs(const nsasm_mesh *mesh, const nsasm_p
     using namespace nsasm;
     return entry<kForward>(mesh, params, precision, {"u", u, 3, false}, {"unused", nullptr, 0, true},
                            {"p", p, 1, false}, {"rhs", rhs, 3, false}, stream);
+}
+
+extern "C" nsasm_status nsasm_assemble_rhs_noalloc(const nsasm_mesh *mesh, const nsasm_params *params,
+                                                   nsasm_precision precision, const void *u, const void *p,
+                                                   void *rhs, void *stream) {
+    using namespace nsasm;
+    return entry<kForward>(mesh, params, precision, {"u", u, 3, false}, {"unused", nullptr, 0, true},
+                           {"p", p, 1, false}, {"rhs", rhs, 3, false}, stream, true);
 }
 
 extern "C" nsasm_status nsasm_assemble_rhs_vjp(const nsasm_mesh *mesh, const nsasm_params *params,
