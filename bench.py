@@ -207,6 +207,11 @@ def parse():
     ap.add_argument("--patch-elems", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 1 GiB (HBM bandwidth and counter calibration)")
+    ap.add_argument("--blocks", type=int, default=0,
+                    help="timed blocks of K steps (0: at least five and at least %d steps in all)" % MIN_TIMED_STEPS)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for profiler passes: only the listed configs, each timed briefly, no headline, "
+                         "extras or oracle; prints one short JSON line")
     return ap.parse_args()
 
 
@@ -260,15 +265,17 @@ class Loaded:
         self.mesh.close()
 
 
-def time_blocks(torch, step, k: int, w: int) -> dict:
+def time_blocks(torch, step, k: int, w: int, nblocks: int = 0) -> dict:
     """W untimed steps, then back-to-back blocks of exactly K steps between
-    HIP events on the launch stream (at least five blocks and MIN_TIMED_STEPS
-    steps), bracketed by device synchronisation.  Per-step times of every
-    block; the median block is the figure, the first block is reported."""
+    HIP events on the launch stream (by default at least five blocks and
+    MIN_TIMED_STEPS steps), bracketed by device synchronisation.  Per-step
+    times of every block; the median block is the figure, the first block is
+    reported."""
     for _ in range(w):
         step()
     torch.cuda.synchronize()
-    nblocks = max(5, math.ceil(MIN_TIMED_STEPS / k))
+    if nblocks <= 0:
+        nblocks = max(5, math.ceil(MIN_TIMED_STEPS / k))
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(nblocks + 1)]
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
@@ -393,7 +400,7 @@ def measure_config(cfg: Config, ld: Loaded, args, torch, api, scale_gbs, res, bl
             fn()
 
     if blocks is None:
-        blocks = time_blocks(torch, step, args.steps, args.warmup)
+        blocks = time_blocks(torch, step, args.steps, args.warmup, args.blocks)
     phases = time_phases(torch, api, calls, args.steps)
     ctr = counter_record(ld.wl.name)
     rec = {"workload": ld.wl.name, "n_elems": ld.ne, "n_nodes": ld.nn, "precision": cfg.precision,
@@ -457,7 +464,7 @@ def main():
     sc_b = torch.empty_like(sc_a)
     for _ in range(3):
         api.stream_scale(sc_a, 3.0, out=sc_b)
-    sk = time_blocks(torch, lambda: api.stream_scale(sc_a, 3.0, out=sc_b), 4, 2)
+    sk = time_blocks(torch, lambda: api.stream_scale(sc_a, 3.0, out=sc_b), 4, 2, 5 if args.profile_run else 0)
     sc_bytes = 16 * sc_a.numel()
     scale_gbs = sc_bytes / (sk["median_ms"] * 1e-3) / 1e9
     hbm_scale = {"bytes_per_call": sc_bytes, "median_ms": sk["median_ms"], "GBs": scale_gbs,
@@ -473,10 +480,14 @@ def main():
         a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
-        cp = time_blocks(torch, lambda: b.copy_(a), 2, 1)
+        cp = time_blocks(torch, lambda: b.copy_(a), 2, 1, 3)
         copy_cal = {"bytes_read": nbytes, "bytes_written": nbytes, "median_ms": cp["median_ms"],
                     "GBs_read_plus_write": 2 * nbytes / (cp["median_ms"] * 1e-3) / 1e9}
         del a, b
+
+    if args.profile_run:
+        profile_run(names, args, torch, api, synth, scale_gbs, res, copy_cal)
+        return
 
     # ---------------------------------------------------------------- headline
     hcfg = CONFIGS[HEADLINE]
@@ -487,7 +498,7 @@ def main():
         for _, fn in calls:
             fn()
 
-    blocks = time_blocks(torch, step, args.steps, args.warmup)
+    blocks = time_blocks(torch, step, args.steps, args.warmup, args.blocks)
     ms_per_step = blocks["median_ms"]
     value = ld.ne / (ms_per_step * 1e-3)
     log(f"[bench] headline {hcfg.name}: {blocks['blocks']} blocks of {args.steps} steps, median "
@@ -542,6 +553,23 @@ def main():
         result["copy_calibration"] = copy_cal
     result.update({k: v for k, v in extras.items() if k != "scatter"})
     print(json.dumps(result), flush=True)
+
+
+def profile_run(names, args, torch, api, synth, scale_gbs, res, copy_cal):
+    """Only the listed configs, in order, without oracle: a short run for
+    profiler passes (each workload's kernels dispatched a few times)."""
+    args.no_cpu_baseline = True
+    loaded, out = {}, {}
+    for i, cname in enumerate(names):
+        cfg = CONFIGS[cname]
+        if cfg.workload not in loaded:
+            loaded[cfg.workload] = Loaded(cfg.workload, args, torch, api, synth)
+        rec = measure_config(cfg, loaded[cfg.workload], args, torch, api, scale_gbs, res)
+        out[cname] = {"workload": rec["workload"], "elements_per_s": rec["elements_per_s"], "kernels": rec["kernels"]}
+        if all(CONFIGS[c].workload != cfg.workload for c in names[i + 1:]):
+            loaded.pop(cfg.workload).close()
+            torch.cuda.empty_cache()
+    print(json.dumps({"profile_run": out, "copy_calibration": copy_cal}), flush=True)
 
 
 def headline_extras(args, torch, api, ld: Loaded, step):

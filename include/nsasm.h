@@ -362,6 +362,26 @@ nsasm_status nsasm_explicit_update(const nsasm_mesh *mesh, const nsasm_params *p
 nsasm_status nsasm_stream_scale(const double *a, double *b, int64_t n, double s, void *stream);
 
 /*
+ * Atomic scatter rate: out[index[k] * ncomp + c] += value for k < n and
+ * c < ncomp, each a device-scope atomic add, one thread per index entry in
+ * index order.  This is the immediate scatter of the paper's final GPU kernel
+ * (Sec. V-D: each element adds its local RHS straight into the global
+ * vector), without the element arithmetic, so a caller can price an atomic:
+ * with index = the mesh-order connectivity (4 entries per element) and
+ * ncomp = 3 it issues exactly the atomics of an atomic-scatter assembly.
+ * index : device, n int32 row numbers; entries outside [0, n_out_rows) are
+ *         skipped.
+ * out   : device, n_out_rows x ncomp, double (NSASM_FP64) or float
+ *         (NSASM_MIXED); accumulated into, not cleared.
+ * ncomp : 1..16.  n, n_out_rows : >= 0; n = 0 does nothing.
+ * Asynchronous on stream.  The order of the additions is unspecified.
+ * Errors: INVALID_ARGUMENT (NULL or non-device pointer, bad sizes, unknown
+ * precision), DEVICE.
+ */
+nsasm_status nsasm_scatter_add(const int32_t *index, int64_t n, int32_t ncomp, nsasm_precision precision,
+                               double value, void *out, int64_t n_out_rows, void *stream);
+
+/*
  * Library helper for measurement, no passage of the paper (the paper times
  * its kernels one by one, Sec. III-A; this lets a caller do the same with HIP
  * events).  event: a hipEvent_t created by the caller (who keeps owning it),

@@ -72,12 +72,13 @@ def _load() -> ctypes.CDLL:
     lib.nsasm_explicit_update.argtypes = [vp, ctypes.POINTER(_Params), st, ctypes.c_double, vp, vp, vp, vp, vp,
                                           vp]
     lib.nsasm_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
+    lib.nsasm_scatter_add.argtypes = [vp, i64, i32, st, ctypes.c_double, vp, i64, vp]
     lib.nsasm_set_phase_event.argtypes = [vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
                  "nsasm_assemble_rhs", "nsasm_assemble_rhs_noalloc", "nsasm_assemble_rhs_vjp",
                  "nsasm_assemble_rhs_vjp_p", "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
-                 "nsasm_stream_scale", "nsasm_set_phase_event"):
+                 "nsasm_stream_scale", "nsasm_scatter_add", "nsasm_set_phase_event"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -355,6 +356,21 @@ def stream_scale(a: torch.Tensor, s: float, out: torch.Tensor = None, stream=Non
     else:
         _dev(out, torch.float64, a.shape, "out")
     _check(lib.nsasm_stream_scale(a.data_ptr(), out.data_ptr(), a.numel(), float(s), _stream(stream)))
+    return out
+
+
+def scatter_add(index: torch.Tensor, out: torch.Tensor, value: float = 1.0, stream=None) -> torch.Tensor:
+    """out[index[k], :] += value with one device-scope atomic add per entry
+    and column (the atomic-rate measurement kernel); index is a 1-D int32
+    tensor, out a 2-D float64 (FP64) or float32 (mixed) tensor.  Entries of
+    index outside [0, out.shape[0]) are skipped."""
+    if index.dim() != 1 or out.dim() != 2:
+        raise ValueError("index must be 1-D and out 2-D")
+    _dev(index, torch.int32, index.shape, "index")
+    prec = _precision_of(out)
+    _dev(out, out.dtype, out.shape, "out")
+    _check(lib.nsasm_scatter_add(index.data_ptr(), index.numel(), out.shape[1], prec, float(value), out.data_ptr(),
+                                 out.shape[0], _stream(stream)))
     return out
 
 

@@ -89,8 +89,33 @@ __device__ inline void global_add(float *p, float v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double cube_root(double v) { return cbrt(v); }
-__device__ inline float cube_root(float v) { return cbrtf(v); }
+// Delta^2 = V^(2/3), the squared filter width of the eddy viscosity.  FP64:
+// the device library's cube root.  FP32 (the mixed path): y = V^(-1/3) from
+// the hardware base-2 logarithm and exponential, refined by one Newton step
+// y <- y (4 - V y^3) / 3 (the estimate's error, about 1e-6 for small V, is
+// squared), then V^(2/3) = V y.  Volumes below 2^-100 are scaled by 2^96
+// first (2^64 after the power), so that the logarithm never sees a denormal.
+__device__ inline double filter_width_sq(double v) {
+    const double d = cbrt(v);
+    return d * d;
+}
+__device__ inline float filter_width_sq(float v) {
+    const bool tiny = v < 0x1p-100f;
+    const float w = tiny ? v * 0x1p96f : v;
+    float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(w) * (-1.0f / 3.0f));
+    y = y * (4.0f - w * (y * y * y)) * (1.0f / 3.0f);
+    const float d2 = w * y;
+    return tiny ? d2 * 0x1p-64f : d2;
+}
+
+// sqrt: correctly rounded in FP64; the hardware square root (1 ulp) in FP32.
+__device__ inline double root(double v) { return sqrt(v); }
+__device__ inline float root(float v) { return __builtin_amdgcn_sqrtf(v); }
+
+// a / b: IEEE division in FP64; in FP32 (the mixed path, whose error is
+// measured, not bounded) the hardware reciprocal (1 ulp) times a.
+__device__ inline double quotient(double a, double b) { return a / b; }
+__device__ inline float quotient(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // ----------------------------------------------------------- element math
 
@@ -127,6 +152,102 @@ __device__ inline void vector_gradient(const T (&gN)[4][3], const T (&ve)[4][3],
 
 enum EddyModel { kNoEddy = 0, kSmagorinsky = 1, kVreman = 2 };
 
+// Cofactor matrix of G: C_ij = G_{i+1,j+1} G_{i+2,j+2} - G_{i+1,j+2} G_{i+2,j+1}
+// (indices mod 3), the 2x2 minors of G with their signs.
+template <typename T>
+__device__ inline void cofactors(const T (&G)[3][3], T (&C)[3][3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            C[i][j] = G[i1][j1] * G[i2][j2] - G[i1][j2] * G[i2][j1];
+        }
+}
+
+// d mu_t / d G is rebuilt from G where it is used (eddy_d), from two scalars,
+// so that its nine entries need not stay live:
+//   Smagorinsky D_ij = k (G_ij + G_ji)              (k = c / |S|),
+//   Vreman      D_ij = k (N_ij - s2 G_ij)            (k = c / (A s), s2 = s^2),
+// with N = (tr(P) I - P) G, P = G G^T, evaluated as the cofactor contraction
+// N_kl = G_{k1 l1} C_{k2 l2} - G_{k1 l2} C_{k2 l1} - G_{k2 l1} C_{k1 l2} + G_{k2 l2} C_{k1 l1}
+// (k1 = k+1, k2 = k+2 mod 3; C the cofactors of G).
+template <typename T>
+struct EddyD {
+    T k;
+    T s2;
+};
+
+// Vreman's B_beta / Delta^4 = e2(P) equals, by the Cauchy-Binet formula, the
+// sum of the squared 2x2 minors of G, |cof G|^2, and (1/2) dB/dG = N above.
+// Both forms are used here instead of minors of P: when G is close to rank
+// one in a scaled direction (elements squashed along one axis), the minors of
+// P cancel to far below their terms while the minors of G do not, so the
+// result keeps its accuracy in FP64 and stays meaningful in FP32.
+template <typename T, int EDDY>
+__device__ inline T eddy_viscosity_k(const T (&G)[3][3], T vol, T rho_c, EddyD<T> &ed) {
+    ed.k = T(0);
+    ed.s2 = T(0);
+    if (EDDY == kNoEddy) return T(0);
+    const T c = rho_c * filter_width_sq(vol);
+    if (EDDY == kSmagorinsky) {
+        // 2 S:S = sum_ij (G_ij + G_ji)^2 / 2 = sum_i 2 G_ii^2 + sum_{i<j} (G_ij + G_ji)^2
+        T ss = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T d = G[i][i];
+            ss += T(2) * d * d;
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const T o = G[i][j] + G[j][i];
+                ss += o * o;
+            }
+        }
+        const T smag = root(ss);
+        ed.k = (smag > T(0)) ? quotient(c, smag) : T(0);
+        return c * smag;
+    }
+    T C[3][3];
+    cofactors(G, C);
+    T A = T(0), B = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            A += G[i][j] * G[i][j];
+            B += C[i][j] * C[i][j];
+        }
+    const bool live = (A > T(0)) && (B > T(0));
+    const T s = live ? root(quotient(B, A)) : T(0);
+    ed.k = live ? quotient(c, A * s) : T(0);
+    ed.s2 = s * s;
+    return c * s;
+}
+
+// All of D = d mu_t / d G from G and the scalars of eddy_viscosity_k.
+template <typename T, int EDDY>
+__device__ inline void eddy_d(const T (&G)[3][3], const EddyD<T> &ed, T (&D)[3][3]) {
+    if (EDDY == kSmagorinsky) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) D[i][j] = ed.k * (G[i][j] + G[j][i]);
+    }
+    if (EDDY == kVreman) {
+        T C[3][3];
+        cofactors(G, C);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int k1 = (k + 1) % 3, k2 = (k + 2) % 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+                const T n = (G[k1][l1] * C[k2][l2] - G[k1][l2] * C[k2][l1]) +
+                            (G[k2][l2] * C[k1][l1] - G[k2][l1] * C[k1][l2]);
+                D[k][l] = ed.k * (n - ed.s2 * G[k][l]);
+            }
+    }
+}
+
 // Eddy viscosity mu_t of the element's constant velocity gradient G, with
 // filter width Delta = V^(1/3) and c = rho_c Delta^2; with WANT_D also
 // D = d mu_t / d G (0 where the model is not differentiable).
@@ -136,54 +257,13 @@ enum EddyModel { kNoEddy = 0, kSmagorinsky = 1, kVreman = 2 };
 //                A = tr P = alpha:alpha and B = e2(P) (sum of the principal
 //                2x2 minors, Vreman's B_beta / Delta^4), mu_t = c s with
 //                s = sqrt(B / A); since dA/dG = 2G and dB/dG = 2(tr(P) I - P)G,
-//                D = c / (A s) ((A - s^2) G - P G).
+//                D = c / (A s) ((tr(P) I - P) G - s^2 G).
 template <typename T, int EDDY, bool WANT_D>
 __device__ inline T eddy_viscosity(const T (&G)[3][3], T vol, T rho_c, T (&D)[3][3]) {
-    if (EDDY == kNoEddy) return T(0);
-    const T delta = cube_root(vol);
-    const T c = rho_c * delta * delta;
-    if (EDDY == kSmagorinsky) {
-        T S[3][3], ss = T(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                S[i][j] = T(0.5) * (G[i][j] + G[j][i]);
-                ss += S[i][j] * S[i][j];
-            }
-        const T smag = sqrt(T(2) * ss);
-        if (WANT_D) {
-            const T k = (smag > T(0)) ? T(2) * c / smag : T(0);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) D[i][j] = k * S[i][j];
-        }
-        return c * smag;
-    }
-    T Pm[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            Pm[i][j] = G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2];
-            Pm[j][i] = Pm[i][j];
-        }
-    const T A = Pm[0][0] + Pm[1][1] + Pm[2][2];
-    const T B = Pm[0][0] * Pm[1][1] - Pm[0][1] * Pm[0][1] + Pm[0][0] * Pm[2][2] - Pm[0][2] * Pm[0][2] +
-                Pm[1][1] * Pm[2][2] - Pm[1][2] * Pm[1][2];
-    const bool live = (A > T(0)) && (B > T(0));
-    const T s = live ? sqrt(B / A) : T(0);
-    if (WANT_D) {
-        const T k = live ? c / (A * s) : T(0);
-        const T diag = A - s * s;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                D[i][j] = k * (diag * G[i][j] - (Pm[i][0] * G[0][j] + Pm[i][1] * G[1][j] + Pm[i][2] * G[2][j]));
-    }
-    return c * s;
+    EddyD<T> ed;
+    const T mu_t = eddy_viscosity_k<T, EDDY>(G, vol, rho_c, ed);
+    if (WANT_D) eddy_d<T, EDDY>(G, ed, D);
+    return mu_t;
 }
 
 // ldu(a, i) returns u_a[i]; it is called for G and U and again where u_a
@@ -286,8 +366,8 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
     }
     asm volatile("" ::: "memory");
     const T sc = P.rho * vol * T(0.05);
-    T D[3][3];
-    const T mu_e = P.mu + eddy_viscosity<T, EDDY, true>(G, vol, P.rho_c, D);
+    EddyD<T> ed;
+    const T mu_e = P.mu + eddy_viscosity_k<T, EDDY>(G, vol, P.rho_c, ed);
     const T sv = mu_e * vol;
     T scU[3];
 #pragma unroll
@@ -335,6 +415,8 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
     }
     if (EDDY != kNoEddy) {
         const T se = vol * phi;
+        T D[3][3];
+        eddy_d<T, EDDY>(G, ed, D);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -534,25 +616,46 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
     });
 }
 
-// acc = sum of the slots [beg, end) of every component, in a fixed order:
-// chunks of four whose loads are independent (the run is read in parallel,
-// not one LDS round trip per slot); indices past the run are clamped to its
-// first slot and the values masked, so every read stays inside the run.
+// acc = sum of the slots [beg, end) of every component, in a fixed order.
+// FP64: chunks of four whose loads are independent (the run is read in
+// parallel, not one LDS round trip per slot); indices past the run are
+// clamped to its first slot and the values masked, so every read stays
+// inside the run.  FP32: blocks of four slots with no masking, then at most
+// one pair and one single slot (fewer instructions; in FP64 the masked form
+// measured faster).
 template <typename T, int NOUT, int KS>
 __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[NOUT]) {
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
-    for (int k = beg; k < end; k += 4) {
-        T v[4][NOUT];
+    if constexpr (std::is_same<T, double>::value) {
+        for (int k = beg; k < end; k += 4) {
+            T v[4][NOUT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = k + j < end;
-            const int kk = in ? k + j : beg;
+            for (int j = 0; j < 4; ++j) {
+                const bool in = k + j < end;
+                const int kk = in ? k + j : beg;
 #pragma unroll
-            for (int i = 0; i < NOUT; ++i) v[j][i] = in ? sval[i][kk] : T(0);
+                for (int i = 0; i < NOUT; ++i) v[j][i] = in ? sval[i][kk] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) acc[i] += (v[0][i] + v[1][i]) + (v[2][i] + v[3][i]);
         }
+    } else {
+        int k = beg;
+        for (; k + 4 <= end; k += 4) {
 #pragma unroll
-        for (int i = 0; i < NOUT; ++i) acc[i] += (v[0][i] + v[1][i]) + (v[2][i] + v[3][i]);
+            for (int i = 0; i < NOUT; ++i)
+                acc[i] += (sval[i][k] + sval[i][k + 1]) + (sval[i][k + 2] + sval[i][k + 3]);
+        }
+        if (k + 2 <= end) {
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) acc[i] += sval[i][k] + sval[i][k + 1];
+            k += 2;
+        }
+        if (k < end) {
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) acc[i] += sval[i][k];
+        }
     }
 }
 
@@ -582,7 +685,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     // which keeps the forward at six waves per SIMD (five otherwise) and the
     // VJP at five (four otherwise).  In FP32 the kernel already runs eight
     // waves and the extra LDS reads would only cost.
-    constexpr bool kLds = (MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value;
+    constexpr bool kLds = ((MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value) ||
+                          (MODE == kVjp && EDDY != kNoEddy);
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C

@@ -1,8 +1,15 @@
+// Machine measurements the roofline analysis rests on.
+//
 // Attainable HBM bandwidth: the Scale kernel b = s a over FP64 arrays, the
 // streaming measurement the paper prices its machine balance with (Sec. III-C:
 // the measured Scale bandwidth against the FP64 peak, 7 flop/B on its GPU).  One
 // read and one write stream per element, no reuse, so with arrays much larger
 // than the last-level cache its rate is the bandwidth a kernel can draw.
+//
+// Atomic scatter rate: out[index[k]][c] += value with device-scope atomic
+// adds, the immediate scatter of the paper's final kernel (Sec. V-D: each
+// element adds its local RHS straight into the global vector) on its own,
+// without the element arithmetic, so its cost can be priced per atomic.
 #include <cstdint>
 
 #include "internal.hpp"
@@ -51,8 +58,48 @@ __global__ __launch_bounds__(kThreads) void k_scale(const double *__restrict__ a
     }
 }
 
+// One thread per index entry: ncomp device-scope atomic adds of `value`
+// (entries outside [0, rows) are skipped).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_add(const int32_t *__restrict__ index, int64_t n, int ncomp,
+                                                          T value, T *out, int64_t rows) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const int64_t row = index[k];
+    if (row < 0 || row >= rows) return;
+    T *dst = out + row * ncomp;
+    for (int c = 0; c < ncomp; ++c) __hip_atomic_fetch_add(dst + c, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace
 }  // namespace nsasm
+
+extern "C" nsasm_status nsasm_scatter_add(const int32_t *index, int64_t n, int32_t ncomp, nsasm_precision precision,
+                                          double value, void *out, int64_t n_out_rows, void *stream) {
+    using namespace nsasm;
+    clear_error();
+    if (n < 0 || n_out_rows < 0)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "n and n_out_rows must be >= 0 (got %lld, %lld)",
+                    static_cast<long long>(n), static_cast<long long>(n_out_rows));
+    if (ncomp < 1 || ncomp > 16) return fail(NSASM_ERR_INVALID_ARGUMENT, "ncomp must be in [1, 16] (got %d)", ncomp);
+    if (precision != NSASM_FP64 && precision != NSASM_MIXED)
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "unknown precision %d", static_cast<int>(precision));
+    if (n == 0) return NSASM_OK;
+    if ((n + kThreads - 1) / kThreads > int64_t(0x7fffffff))
+        return fail(NSASM_ERR_INVALID_ARGUMENT, "n = %lld is too large", static_cast<long long>(n));
+    NSASM_TRY(check_device_ptr(index, "index"));
+    NSASM_TRY(check_device_ptr(out, "out"));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const unsigned blocks = static_cast<unsigned>((n + kThreads - 1) / kThreads);
+    if (precision == NSASM_FP64)
+        k_scatter_add<double><<<blocks, kThreads, 0, st>>>(index, n, ncomp, value, static_cast<double *>(out),
+                                                           n_out_rows);
+    else
+        k_scatter_add<float><<<blocks, kThreads, 0, st>>>(index, n, ncomp, static_cast<float>(value),
+                                                          static_cast<float *>(out), n_out_rows);
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, "k_scatter_add launch");
+}
 
 extern "C" nsasm_status nsasm_stream_scale(const double *a, double *b, int64_t n, double s, void *stream) {
     using namespace nsasm;

@@ -261,6 +261,13 @@ def test_anisotropic_elements_vreman():
     e_gpu, e_ora = oracle.rel_l2(got, ref), oracle.rel_l2(ora, ref)
     log(f"anisotropic vreman vs high precision: kernel {e_gpu:.2e}, oracle {e_ora:.2e}")
     assert e_gpu <= max(1e-13, 10 * e_ora)
+    # mixed precision: the kernel's cofactor form of B keeps FP32 meaningful here
+    t32 = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32))
+    got32 = mesh.from_mesh_order(api.assemble_rhs(mesh, t32(u), t32(p), api.Params(rho, mu, cs, synth.BODY_FORCE,
+                                                                                  "vreman"))).double().cpu().numpy()
+    e32 = oracle.rel_l2(got32, ref)
+    log(f"  mixed: {e32:.2e}")
+    assert e32 <= TOL_MIXED
 
 
 def test_auto_halves_patches_for_a_tet_strip():
