@@ -659,6 +659,30 @@ def headline_extras(args, torch, api, ld: Loaded, step):
         + f"; jvp {tj * 1e3:.1f} us, vjp_p {tp * 1e3:.1f} us, explicit update {tu * 1e3:.1f} us, "
         f"autograd forward + backward {ta * 1e3:.1f} us")
 
+    # the immediate atomic scatter of the paper's final kernel on its own:
+    # device-scope atomic adds into an (Nn, 3) vector, 4 Ne index entries x 3
+    # components (the atomics of one atomic-scatter assembly call), FP64 and
+    # FP32, for three index patterns
+    conn_m, _ = mesh.connectivity()
+    n_idx = 4 * ne
+    k = torch.arange(n_idx, device=dev, dtype=torch.int64)
+    patterns = {"mesh_connectivity": conn_m.reshape(-1).contiguous(),
+                "contiguous": (k % ld.nn).to(torch.int32),
+                "strided_4099": ((k * 4099) % ld.nn).to(torch.int32)}
+    del k, conn_m
+    atom = {"atomics_per_call": 3 * n_idx, "rows": ld.nn}
+    for dt, tag in ((torch.float64, "fp64"), (torch.float32, "fp32")):
+        acc_buf = torch.zeros((ld.nn, 3), dtype=dt, device=dev)
+        for name, idx in patterns.items():
+            t = mean_ms(lambda: api.scatter_add(idx, acc_buf), 10)
+            atom[f"{tag}_{name}"] = {"ms": t, "atomics_per_s": 3 * n_idx / (t * 1e-3),
+                                     "ns_per_element_12_atomics": t * 1e6 / ne}
+        del acc_buf
+    del patterns
+    extras["atomic_scatter"] = atom
+    log("[bench] atomic scatter (G atomics/s): " + ", ".join(
+        f"{k_}: {v['atomics_per_s'] / 1e9:.1f}" for k_, v in atom.items() if isinstance(v, dict)))
+
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     u_user = torch.from_numpy(np.ascontiguousarray(ld.u)).to(dev)
     mesh.to_mesh_order(u_user)

@@ -71,19 +71,37 @@ def test_vjp_fp64_full(name):
     assert err <= 1e-12
 
 
-def test_mixed_full_160():
-    """Mixed precision on the 160^3 jittered mesh with Smagorinsky: FP64
-    geometry, FP32 fields/arithmetic/scatter; error against the FP64 oracle."""
+def _node_err(got, ref):
+    """max over nodes of |got - ref| (max norm over components) / max |ref|."""
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+# Mixed precision is not bounded by the paper; these gates sit at about ten
+# times the errors measured at each size (FP32 unit roundoff 6e-8), so that a
+# regression of the FP64-geometry / FP32-arithmetic contract fails instead of
+# passing under a loose smoke gate.
+MIXED_GATES = {"cube160_jit_perm_smag": (3e-6, 1e-6, 8e-6, 1.5e-6),   # measured 3.3e-7, 8.9e-8, 8.3e-7, 1.3e-7
+               "cube96_jit_perm": (3e-6, 1e-6, 8e-6, 1.5e-6)}
+
+
+@pytest.mark.parametrize("name", ["cube160_jit_perm_smag", "cube96_jit_perm"])
+def test_mixed_full(name):
+    """Mixed precision at full size (160^3 jittered mesh with Smagorinsky, and
+    the 96^3 jittered mesh): FP64 geometry, FP32 fields/arithmetic/scatter;
+    relative L2 and per-node error against the FP64 oracle."""
     from paper_2403_08777_amd import api
 
-    wl, m, u, p, lam, mesh = _case("cube160_jit_perm_smag")
+    wl, m, u, p, lam, mesh = _case(name)
     prm, oprm = _params(wl)
     r32 = _run(mesh, lambda ms, a, b: api.assemble_rhs(ms, a, b, prm), torch.float32, u, p)
     g32 = _run(mesh, lambda ms, a, b: api.assemble_rhs_vjp(ms, a, b, prm), torch.float32, u, lam)
-    er = oracle.rel_l2(r32, oracle.rhs(m.coords, m.conn, u, p, oprm))
-    eg = oracle.rel_l2(g32, oracle.vjp(m.coords, m.conn, u, lam, oprm))
-    log(f"cube160 mixed rel_l2: rhs {er:.3e}, grad {eg:.3e}")
-    assert er <= 1e-4 and eg <= 1e-4
+    rr = oracle.rhs(m.coords, m.conn, u, p, oprm)
+    gr = oracle.vjp(m.coords, m.conn, u, lam, oprm)
+    er, eg = oracle.rel_l2(r32, rr), oracle.rel_l2(g32, gr)
+    nr, ng = _node_err(r32, rr), _node_err(g32, gr)
+    log(f"{name} mixed: rel_l2 rhs {er:.3e}, grad {eg:.3e}; per node rhs {nr:.3e}, grad {ng:.3e}")
+    tr, tg, tnr, tng = MIXED_GATES[name]
+    assert er <= tr and eg <= tg and nr <= tnr and ng <= tng
 
 
 def test_vreman_full_160():
