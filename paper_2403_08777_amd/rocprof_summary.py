@@ -144,7 +144,7 @@ def counters(args):
     l2 = next(((h, m) for h, m in (("TCC_HIT_sum", "TCC_MISS_sum"), ("TCC_HIT", "TCC_MISS"))
                if h in med and m in med), None)
     shown = [c for c in names if c not in ("SQ_WAVES", "FETCH_SIZE", "WRITE_SIZE") and not c.startswith("TCC_")]
-    rec = {"workload": args.workload, "source_sha256": source_digest(), "commands": args.command,
+    rec = {"workload": args.workload, "source_sha256": args.source_sha256 or source_digest(), "commands": args.command,
            "trace_command": args.trace_command,
            "copy_calibration": {ctr: {"copy_bytes": COPY_BYTES, "counter_kib": kib, "bytes_per_kib": sc * 1024.0}
                                 for ctr, (sc, kib) in scale.items()},
@@ -215,6 +215,8 @@ def main():
     c.add_argument("--trace-command", default="")
     c.add_argument("--kernels", default=r"^k_assemble_patch<|^k_gather_partials<")
     c.add_argument("--json-out", required=True, help="the JSON record bench.py reads (counters_<workload>.json)")
+    c.add_argument("--source-sha256", default="",
+                   help="digest of the HIP sources the passes ran with (default: the sources here now)")
     args = ap.parse_args()
     {"stats": stats, "counters": counters}[args.cmd](args)
 
