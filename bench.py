@@ -15,7 +15,7 @@ the first block is reported beside it.
   C4  96^3 cube, jittered, relabelled, FP64 forward + VJP (the headline)
   C5  the C3 mesh, mixed precision forward + VJP
 each with elements/s (median block), each kernel's duration from HIP events
-recorded between the kernels of the calls (nsasm_set_phase_event), the
+recorded at the kernels' own start and end (nsasm_set_kernel_events), the
 roofline of the dominant kernel, the relative L2 error against the FP64
 oracle over the whole mesh and the oracle's own rate on the host's threads
 (and on one thread for C1 and C2).  Prints one JSON line.
@@ -292,30 +292,36 @@ def time_blocks(torch, step, k: int, w: int, nblocks: int = 0) -> dict:
 
 
 def time_phases(torch, api, calls, k: int) -> dict:
-    """Each call's two kernels timed inside a replica of K steps: HIP events on
-    the launch stream before each call, between its element kernel and its
-    gather kernel (nsasm_set_phase_event) and after it.  Mean and median
-    duration of each kernel over the K steps."""
+    """Each call's two kernels timed live inside a replica of the step,
+    repeated max(K, 100) times right after 20 untimed steps (no
+    synchronisation in between, so the clocks stay where the timed blocks
+    had them): nsasm_set_kernel_events has the library launch the element
+    kernel and the gather kernel with HIP start/stop events that are recorded
+    at the kernel's own start and end on the launch stream.  Mean and median
+    duration of each kernel over the repetitions."""
     n = len(calls)
-    rows = [[torch.cuda.Event(enable_timing=True) for _ in range(1 + 2 * n)] for _ in range(k)]
+    reps = max(k, 100)
+    rows = [[torch.cuda.Event(enable_timing=True) for _ in range(4 * n)] for _ in range(reps)]
     for row in rows:          # HIP events are created on their first record
         for e in row:
             e.record()
     torch.cuda.synchronize()
-    for row in rows:
-        row[0].record()
-        for c, (_, fn) in enumerate(calls):
-            api.set_phase_event(row[1 + 2 * c])
+    for _ in range(20):
+        for _, fn in calls:
             fn()
-            row[2 + 2 * c].record()
+    for row in rows:
+        for c, (_, fn) in enumerate(calls):
+            api.set_kernel_events(*row[4 * c:4 * c + 4])
+            fn()
     torch.cuda.synchronize()
     out = {}
     for c, (name, _) in enumerate(calls):
-        el = [row[2 * c].elapsed_time(row[1 + 2 * c]) for row in rows]
-        ga = [row[1 + 2 * c].elapsed_time(row[2 + 2 * c]) for row in rows]
+        el = [row[4 * c].elapsed_time(row[4 * c + 1]) for row in rows]
+        ga = [row[4 * c + 2].elapsed_time(row[4 * c + 3]) for row in rows]
         out[name] = {"element_kernel_ms": float(np.mean(el)), "element_kernel_median_ms": float(np.median(el)),
                      "gather_kernel_ms": float(np.mean(ga)), "gather_kernel_median_ms": float(np.median(ga)),
-                     "call_ms": float(np.mean(el) + np.mean(ga))}
+                     "call_ms": float(np.mean(el) + np.mean(ga)),
+                     "call_median_ms": float(np.median(el) + np.median(ga)), "repetitions": reps}
     return out
 
 

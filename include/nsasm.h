@@ -384,16 +384,20 @@ nsasm_status nsasm_scatter_add(const int32_t *index, int64_t n, int32_t ncomp, n
 /*
  * Library helper for measurement, no passage of the paper (the paper times
  * its kernels one by one, Sec. III-A; this lets a caller do the same with HIP
- * events).  event: a hipEvent_t created by the caller (who keeps owning it),
- * or NULL to cancel.  The next assembly call made on this thread
- * (nsasm_assemble_rhs, _vjp, _vjp_p, _jvp, nsasm_explicit_update) records it
- * on its stream right after its element kernel: with PATCH_GATHER between the
- * patch kernel and the node-gather kernel, with the one-kernel scatters after
- * that kernel.  The call consumes the event whether it succeeds or not.  The
- * event is not recorded by nsasm_mesh_create or any other function.  Always
- * returns NSASM_OK.
+ * events, live).  The next assembly call made on this thread
+ * (nsasm_assemble_rhs, _noalloc, _vjp, _vjp_p, _jvp, nsasm_explicit_update)
+ * launches its element kernel (patch kernel or per-element atomic kernel)
+ * with element_start / element_stop and its node kernel (the gather of the
+ * gather scatter, or the update kernel) with gather_start / gather_stop
+ * through hipExtLaunchKernelGGL, which records each event at its kernel's
+ * own start or end: hipEventElapsedTime(start, stop) is that kernel's
+ * duration.  Each argument is a hipEvent_t created by the caller (who keeps
+ * owning it) or NULL (not recorded); four NULLs cancel a pending request.
+ * The call consumes the events whether it succeeds or not; no other function
+ * records them.  Always returns NSASM_OK.
  */
-nsasm_status nsasm_set_phase_event(void *event);
+nsasm_status nsasm_set_kernel_events(void *element_start, void *element_stop, void *gather_start,
+                                     void *gather_stop);
 
 /* Library helper, no passage of the paper.  Message for the last non-OK
  * status on this thread ("" if none); the string is owned by the library and

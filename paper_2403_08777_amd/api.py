@@ -73,12 +73,12 @@ def _load() -> ctypes.CDLL:
                                           vp]
     lib.nsasm_stream_scale.argtypes = [vp, vp, i64, ctypes.c_double, vp]
     lib.nsasm_scatter_add.argtypes = [vp, i64, i32, st, ctypes.c_double, vp, i64, vp]
-    lib.nsasm_set_phase_event.argtypes = [vp]
+    lib.nsasm_set_kernel_events.argtypes = [vp, vp, vp, vp]
     for name in ("nsasm_mesh_create", "nsasm_mesh_destroy", "nsasm_mesh_info", "nsasm_mesh_permutation",
                  "nsasm_mesh_connectivity", "nsasm_to_mesh_order", "nsasm_from_mesh_order",
                  "nsasm_assemble_rhs", "nsasm_assemble_rhs_noalloc", "nsasm_assemble_rhs_vjp",
                  "nsasm_assemble_rhs_vjp_p", "nsasm_assemble_rhs_jvp", "nsasm_mesh_lumped_volume", "nsasm_explicit_update",
-                 "nsasm_stream_scale", "nsasm_scatter_add", "nsasm_set_phase_event"):
+                 "nsasm_stream_scale", "nsasm_scatter_add", "nsasm_set_kernel_events"):
         getattr(lib, name).restype = st
     lib.nsasm_last_error.restype = ctypes.c_char_p
     lib.nsasm_last_error.argtypes = []
@@ -374,18 +374,20 @@ def scatter_add(index: torch.Tensor, out: torch.Tensor, value: float = 1.0, stre
     return out
 
 
-def set_phase_event(event) -> None:
-    """Have the next assembly call on this thread record ``event`` (a
+def set_kernel_events(element_start=None, element_stop=None, gather_start=None, gather_stop=None) -> None:
+    """Have the next assembly call on this thread record these events (each a
     ``torch.cuda.Event`` already recorded once, so that its HIP event exists,
-    or None to cancel) on its stream between its element kernel and its gather
-    kernel (nsasm_set_phase_event)."""
-    if event is None:
-        _check(lib.nsasm_set_phase_event(None))
-        return
-    handle = event.cuda_event
-    if not handle:
-        raise ValueError("record the event once before passing it (its HIP event is created lazily)")
-    _check(lib.nsasm_set_phase_event(handle))
+    or None) at the start and end of its element kernel and of its gather
+    kernel (nsasm_set_kernel_events); no arguments cancel."""
+    handles = []
+    for ev in (element_start, element_stop, gather_start, gather_stop):
+        if ev is None:
+            handles.append(None)
+            continue
+        if not ev.cuda_event:
+            raise ValueError("record the event once before passing it (its HIP event is created lazily)")
+        handles.append(ev.cuda_event)
+    _check(lib.nsasm_set_kernel_events(*handles))
 
 
 class NSAssembleRHS(torch.autograd.Function):

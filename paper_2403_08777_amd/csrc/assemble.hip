@@ -44,6 +44,8 @@
 #include <mutex>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace nsasm {
@@ -923,60 +925,57 @@ struct Update {
     T *u_new;
 };
 
-// Recorded on the launch stream after the element kernel of a call (see
-// nsasm_set_phase_event); null for none.
-nsasm_status record_phase(hipEvent_t phase, hipStream_t s) {
-    if (!phase) return NSASM_OK;
-    hipError_t err = hipEventRecord(phase, s);
-    return err == hipSuccess ? NSASM_OK : hip_fail(err, "hipEventRecord of the phase event");
+// One kernel launch of kThreads-wide workgroups on `s`.  With a start or
+// stop event (nsasm_set_kernel_events) it goes through hipExtLaunchKernelGGL,
+// which records the events at the kernel's own start and end.
+template <typename... KArgs, typename... Args>
+nsasm_status launch_kernel(void (*kernel)(KArgs...), unsigned grid, hipStream_t s, hipEvent_t start,
+                           hipEvent_t stop, const char *what, Args... args) {
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, s, start, stop, 0, args...);
+    else
+        kernel<<<grid, kThreads, 0, s>>>(args...);
+    hipError_t err = hipGetLastError();
+    return err == hipSuccess ? NSASM_OK : hip_fail(err, what);
 }
 
 // With the gather scatter and `up` set, the gather kernel applies the
-// explicit update instead of writing `out`.  `phase` (may be null) is
-// recorded between the element kernel and the gather kernel.
-// `partial` (may be null: the mesh's own buffer) receives the per-patch node
-// sums of the gather scatter.
+// explicit update instead of writing `out`.  `ev` times the element kernel
+// and the gather kernel (events may be null).  `partial` (may be null: the
+// mesh's own buffer) receives the per-patch node sums of the gather scatter.
 template <typename T, int EDDY, int CONV, int MODE>
 nsasm_status launch(const nsasm_mesh *m, const KParams<T> &kp, NodeFields<T> F, T *out, bool accumulate,
-                    const Update<T> *up, hipEvent_t phase, hipStream_t s, T *partial = nullptr) {
+                    const Update<T> *up, const KernelEvents &ev, hipStream_t s, T *partial = nullptr) {
     constexpr int NOUT = Fields<MODE>::NOUT;
     if (m->scatter == NSASM_SCATTER_PATCH_GATHER) {
         if (!partial) partial = reinterpret_cast<T *>(m->partial);
-        k_assemble_patch<T, EDDY, CONV, MODE, true><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
-            m->n_elems, m->n_patches, m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
-            m->elem_loc, m->x, F, kp, partial);
-        hipError_t err = hipGetLastError();
-        if (err != hipSuccess) return hip_fail(err, "patch kernel launch");
-        NSASM_TRY(record_phase(phase, s));
+        NSASM_TRY(launch_kernel(k_assemble_patch<T, EDDY, CONV, MODE, true>, xcd_grid(m->n_patches), s,
+                                ev.element_start, ev.element_stop, "patch kernel launch", m->n_elems, m->n_patches,
+                                m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
+                                m->elem_loc, m->x, F, kp, partial));
         const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
         if constexpr (MODE == kForward) {
-            if (up) {
-                k_gather_update<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial,
-                                                                        m->lumped, up->rho, up->dt, up->u,
-                                                                        up->mask, up->rhs, up->u_new);
-                err = hipGetLastError();
-                return err == hipSuccess ? NSASM_OK : hip_fail(err, "update kernel launch");
-            }
+            if (up)
+                return launch_kernel(k_gather_update<T>, xcd_grid(tiles), s, ev.gather_start, ev.gather_stop,
+                                     "update kernel launch", m->n_nodes, m->node_ref_off, partial, m->lumped, up->rho,
+                                     up->dt, up->u, up->mask, up->rhs, up->u_new);
         }
-        k_gather_partials<T, NOUT><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, m->node_ref_off, partial, out,
-                                                                        accumulate ? 1 : 0);
-    } else if (m->scatter == NSASM_SCATTER_PATCH) {
-        k_assemble_patch<T, EDDY, CONV, MODE, false><<<xcd_grid(m->n_patches), kThreads, 0, s>>>(
-            m->n_elems, m->n_patches, m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos,
-            m->elem_loc, m->x, F, kp, out);
-    } else {
-        const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
-        k_assemble_atomic<T, EDDY, CONV, MODE><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_elems, m->conn, m->x, F,
-                                                                                   kp, out);
+        return launch_kernel(k_gather_partials<T, NOUT>, xcd_grid(tiles), s, ev.gather_start, ev.gather_stop,
+                             "gather kernel launch", m->n_nodes, m->node_ref_off, partial, out, accumulate ? 1 : 0);
     }
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return hip_fail(err, "assembly kernel launch");
-    return m->scatter == NSASM_SCATTER_PATCH_GATHER ? NSASM_OK : record_phase(phase, s);
+    if (m->scatter == NSASM_SCATTER_PATCH)
+        return launch_kernel(k_assemble_patch<T, EDDY, CONV, MODE, false>, xcd_grid(m->n_patches), s,
+                             ev.element_start, ev.element_stop, "patch kernel launch", m->n_elems, m->n_patches,
+                             m->patch_elems, m->patch_stride, m->patch_rec, m->patch_ref, m->elem_pos, m->elem_loc,
+                             m->x, F, kp, out);
+    const int64_t tiles = (m->n_elems + kThreads - 1) / kThreads;
+    return launch_kernel(k_assemble_atomic<T, EDDY, CONV, MODE>, xcd_grid(tiles), s, ev.element_start,
+                         ev.element_stop, "assembly kernel launch", m->n_elems, m->conn, m->x, F, kp, out);
 }
 
 template <typename T, int CONV, int MODE>
 nsasm_status launch_eddy(const nsasm_mesh *m, const nsasm_params &p, const KParams<T> &kp, NodeFields<T> F, T *o,
-                         const Update<T> *up, hipEvent_t ph, hipStream_t s, T *partial) {
+                         const Update<T> *up, const KernelEvents &ph, hipStream_t s, T *partial) {
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     if (p.smagorinsky_cs > 0.0 && p.eddy_model == NSASM_EDDY_VREMAN)
         return launch<T, kVreman, CONV, MODE>(m, kp, F, o, accumulate, up, ph, s, partial);
@@ -988,7 +987,7 @@ nsasm_status launch_eddy(const nsasm_mesh *m, const nsasm_params &p, const KPara
 // Physics selection (convective form, eddy viscosity) of a launch.
 template <typename T, int MODE>
 nsasm_status dispatch(const nsasm_mesh *m, const nsasm_params &p, NodeFields<T> F, T *o, const Update<T> *up,
-                      hipEvent_t ph, hipStream_t s, T *partial = nullptr) {
+                      const KernelEvents &ph, hipStream_t s, T *partial = nullptr) {
     const KParams<T> kp = kernel_params<T>(p);
     if constexpr (MODE == kVjpP) {
         // the pressure term depends on neither the viscosity nor the convective form
@@ -1011,7 +1010,7 @@ nsasm_status fill_zero(T *o, int64_t n, hipStream_t s) {
 
 template <typename T, int MODE>
 nsasm_status run(const nsasm_mesh *m, const nsasm_params &p, const void *fa, const void *fb, const void *fc,
-                 void *out, hipEvent_t ph, hipStream_t s, void *partial) {
+                 void *out, const KernelEvents &ph, hipStream_t s, void *partial) {
     T *o = static_cast<T *>(out);
     const bool accumulate = (p.flags & NSASM_ACCUMULATE) != 0;
     // the gather kernel writes every node, so it needs no zero-fill
@@ -1062,7 +1061,7 @@ nsasm_status scratch_address(int device, void **out) {
 // the gather scatter, else assembled into `rhs` and updated by k_update.
 template <typename T>
 nsasm_status run_update(const nsasm_mesh *m, const nsasm_params &p, double dt, const void *u, const void *pr,
-                        const uint8_t *mask, void *rhs, void *u_new, hipEvent_t ph, hipStream_t s) {
+                        const uint8_t *mask, void *rhs, void *u_new, const KernelEvents &ph, hipStream_t s) {
     const NodeFields<T> F{static_cast<const T *>(u), nullptr, static_cast<const T *>(pr)};
     T *r = static_cast<T *>(rhs);
     const Update<T> up{p.rho, dt, static_cast<const T *>(u), mask, r, static_cast<T *>(u_new)};
@@ -1070,9 +1069,9 @@ nsasm_status run_update(const nsasm_mesh *m, const nsasm_params &p, double dt, c
     NSASM_TRY(fill_zero(r, 3 * m->n_nodes, s));
     NSASM_TRY((dispatch<T, kForward>(m, p, F, r, nullptr, ph, s)));
     const int64_t tiles = (m->n_nodes + kThreads - 1) / kThreads;
-    k_update<T><<<xcd_grid(tiles), kThreads, 0, s>>>(m->n_nodes, r, m->lumped, p.rho, dt, up.u, mask, up.u_new);
-    hipError_t err = hipGetLastError();
-    return err == hipSuccess ? NSASM_OK : hip_fail(err, "update kernel launch");
+    return launch_kernel(k_update<T>, xcd_grid(tiles), s, ph.gather_start, ph.gather_stop, "update kernel launch",
+                         m->n_nodes, static_cast<const T *>(r), static_cast<const double *>(m->lumped), p.rho, dt,
+                         up.u, mask, up.u_new);
 }
 
 // One device array argument of an entry point: name, pointer, components per
@@ -1089,7 +1088,7 @@ struct Arg {
 template <int MODE>
 nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, Arg a, Arg b, Arg c,
                    Arg out, void *stream, bool no_alloc = false) {
-    const hipEvent_t ph = take_phase_event();  // consumed by this call, whatever its outcome
+    const KernelEvents ph = take_kernel_events();  // consumed by this call, whatever its outcome
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
     if (prec != NSASM_FP64 && prec != NSASM_MIXED)
@@ -1129,7 +1128,7 @@ nsasm_status entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precis
 
 nsasm_status update_entry(const nsasm_mesh *m, const nsasm_params *params, nsasm_precision prec, double dt,
                           const void *u, const void *p, const uint8_t *mask, void *rhs, void *u_new, void *stream) {
-    const hipEvent_t ph = take_phase_event();  // consumed by this call, whatever its outcome
+    const KernelEvents ph = take_kernel_events();  // consumed by this call, whatever its outcome
     if (!m) return fail(NSASM_ERR_INVALID_ARGUMENT, "mesh is NULL");
     NSASM_TRY(check_params(params));
     if (params->flags != 0) return fail(NSASM_ERR_INVALID_ARGUMENT, "flags must be 0 for the explicit update");
@@ -1170,7 +1169,7 @@ nsasm_status compute_lumped_volume(nsasm_mesh *m, hipStream_t s) {
     if (m->scatter != NSASM_SCATTER_PATCH_GATHER) NSASM_TRY(fill_zero(m->lumped, m->n_nodes, s));
     const KParams<double> kp{};
     const NodeFields<double> F{nullptr, nullptr, nullptr};
-    return launch<double, kNoEddy, kAdvective, kMass>(m, kp, F, m->lumped, false, nullptr, nullptr, s);
+    return launch<double, kNoEddy, kAdvective, kMass>(m, kp, F, m->lumped, false, nullptr, KernelEvents{}, s);
 }
 
 }  // namespace nsasm

@@ -16,9 +16,18 @@ namespace nsasm {
 nsasm_status fail(nsasm_status status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 
-// The event set by nsasm_set_phase_event on this thread (or null), which the
-// caller then owns; the pending event is cleared.
-hipEvent_t take_phase_event();
+// Caller-owned HIP events that time the kernels of the next assembly call on
+// a thread (nsasm_set_kernel_events); any may be null.
+struct KernelEvents {
+    hipEvent_t element_start = nullptr;
+    hipEvent_t element_stop = nullptr;
+    hipEvent_t gather_start = nullptr;
+    hipEvent_t gather_stop = nullptr;
+};
+
+// The events set by nsasm_set_kernel_events on this thread (all null if
+// none); the pending events are cleared.
+KernelEvents take_kernel_events();
 
 // Map a HIP error to NSASM_ERR_DEVICE (or OUT_OF_MEMORY) with context.
 nsasm_status hip_fail(hipError_t err, const char *what);

@@ -10,7 +10,7 @@ namespace nsasm {
 
 namespace {
 thread_local std::string g_message;
-thread_local hipEvent_t g_phase_event = nullptr;
+thread_local KernelEvents g_kernel_events;
 std::atomic<long> g_alloc_count{0};
 
 long fail_alloc_at() {
@@ -34,9 +34,9 @@ nsasm_status fail(nsasm_status status, const char *fmt, ...) {
 
 void clear_error() { g_message.clear(); }
 
-hipEvent_t take_phase_event() {
-    hipEvent_t e = g_phase_event;
-    g_phase_event = nullptr;
+KernelEvents take_kernel_events() {
+    KernelEvents e = g_kernel_events;
+    g_kernel_events = KernelEvents{};
     return e;
 }
 
@@ -87,8 +87,11 @@ void device_free(void *p) {
 
 extern "C" const char *nsasm_last_error(void) { return nsasm::g_message.c_str(); }
 
-extern "C" nsasm_status nsasm_set_phase_event(void *event) {
-    nsasm::g_phase_event = static_cast<hipEvent_t>(event);
+extern "C" nsasm_status nsasm_set_kernel_events(void *element_start, void *element_stop, void *gather_start,
+                                                void *gather_stop) {
+    nsasm::g_kernel_events = nsasm::KernelEvents{
+        static_cast<hipEvent_t>(element_start), static_cast<hipEvent_t>(element_stop),
+        static_cast<hipEvent_t>(gather_start), static_cast<hipEvent_t>(gather_stop)};
     nsasm::clear_error();
     return NSASM_OK;
 }

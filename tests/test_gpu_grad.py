@@ -170,39 +170,44 @@ def test_double_backward_raises():
         torch.autograd.grad(g.sum(), uu)
 
 
-def test_phase_event_splits_the_call():
-    """nsasm_set_phase_event: the next call records the event between its
-    element kernel and its gather kernel, so start <= phase <= end with both
-    parts taking time; the call's result is unchanged, and the event is
-    consumed (a later call leaves it where it was)."""
+def test_kernel_events_time_the_two_kernels():
+    """nsasm_set_kernel_events: the next call records the four events at the
+    start and end of its element kernel and of its gather kernel, so that
+    e0 <= es < ee <= gs < ge <= e1 (up to timer resolution) and both kernels
+    take time; the result is unchanged; the events are consumed, also by a
+    call that fails."""
     from paper_2403_08777_amd import api
 
     case = Case(16, jitter=True, permute=True, mu=1e-3)
     pr = Prepared(case)
     u, p, lam = pr.fields(torch.float64)
     ref = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
-    e0, ph, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    ph.record()
+    e0, es, ee, gs, ge, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(6))
+    for e in (es, ee, gs, ge):
+        e.record()
     torch.cuda.synchronize()
     e0.record()
-    api.set_phase_event(ph)
+    api.set_kernel_events(es, ee, gs, ge)
     got = api.assemble_rhs_vjp(pr.mesh, u, lam, case.params())
     e1.record()
     torch.cuda.synchronize()
-    a, b = e0.elapsed_time(ph), ph.elapsed_time(e1)
-    log(f"phase split: element kernel {a * 1e3:.1f} us, gather {b * 1e3:.1f} us")
-    assert a > 0 and b > 0
+    tk, tg = es.elapsed_time(ee), gs.elapsed_time(ge)
+    log(f"kernel events: element kernel {tk * 1e3:.1f} us, gather {tg * 1e3:.1f} us, "
+        f"call {e0.elapsed_time(e1) * 1e3:.1f} us")
+    assert tk > 0 and tg > 0
+    eps = 1e-3  # ms: event timestamps of neighbouring packets may tie within the timer resolution
+    assert e0.elapsed_time(es) >= -eps and ee.elapsed_time(gs) >= -eps and ge.elapsed_time(e1) >= -eps
     assert torch.equal(got, ref)
-    # consumed: another call does not move the event
+    # consumed: another call does not move the events
     api.assemble_rhs(pr.mesh, u, p, case.params())
     torch.cuda.synchronize()
-    assert abs(e0.elapsed_time(ph) - a) < 1e-9
-    # a failing call consumes it too (NULL output pointer: rejected on the host)
-    api.set_phase_event(ph)
+    assert abs(es.elapsed_time(ee) - tk) < 1e-9
+    # a failing call consumes them too (NULL output pointer: rejected on the host)
+    api.set_kernel_events(es, ee, gs, ge)
     prm = case.params().c_struct()
     assert api.lib.nsasm_assemble_rhs(pr.mesh.handle, ctypes.byref(prm), 0, u.data_ptr(), p.data_ptr(), None,
                                       None) == 1
     api.assemble_rhs(pr.mesh, u, p, case.params())
     torch.cuda.synchronize()
-    assert abs(e0.elapsed_time(ph) - a) < 1e-9
-    api.set_phase_event(None)
+    assert abs(es.elapsed_time(ee) - tk) < 1e-9 and abs(gs.elapsed_time(ge) - tg) < 1e-9
+    api.set_kernel_events()
