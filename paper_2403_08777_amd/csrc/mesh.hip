@@ -261,18 +261,29 @@ __global__ __launch_bounds__(kThreads) void k_patch_count(const int4 *conn, int6
 
 // Pass 2: for each patch write its distinct nodes (ascending), the start of
 // each node's run of slots in node-sorted order, and for every element the
-// sorted positions of its four (element, vertex) slots.  An assembly
-// workgroup stores element contributions at those positions and then sums
-// each node's run: a deterministic in-LDS reduction without atomics.
-// Patches with more than kMaxPatchNodes nodes are rejected (from pass 1) on
-// the host before this runs.
+// positions of its four (element, vertex) slots.  An assembly workgroup
+// stores element contributions at those positions and then sums each node's
+// run: a deterministic in-LDS reduction without atomics.  Which position of
+// its node's run each (element, vertex) pair takes is free; it is chosen so
+// that the stores of one instruction -- vertex a of the 32 elements of a
+// half-wave, which the LDS serves together, a double's bank pair being its
+// slot modulo 32 -- fall into different banks where possible: greedily, half
+// -wave by half-wave and vertex by vertex, each pair takes the free position
+// of its run whose bank this instruction has used least (the lowest such
+// position on ties).  Patches with more than kMaxPatchNodes nodes are rejected
+// (from pass 1) on the host before this runs.
 __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64_t ne, int elems,
                                                           const uint32_t *offset, int32_t *nodes,
                                                           int32_t *node_start, ushort4 *elem_pos) {
     __shared__ uint64_t keys[kPatchSlots];
     __shared__ uint16_t pos_of_slot[kPatchSlots];
+    __shared__ uint16_t run_first[kPatchSlots];   // by element slot: its node's run [first, first + len)
+    __shared__ uint16_t run_len[kPatchSlots];
+    __shared__ uint32_t used[kPatchSlots / 32];    // run positions already taken
+    __shared__ uint32_t bank_use[32];              // stores per bank in the current instruction
     __shared__ uint32_t lds4[4];
     const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
+    const int nel = static_cast<int>(min<int64_t>(elems, ne - first));
     patch_sorted_pairs(conn, ne, first, elems, keys);
     bool head[4];
     uint32_t heads = 0;
@@ -284,6 +295,8 @@ __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64
     uint32_t total;
     uint32_t u = block_exclusive_scan_256(heads, lds4, &total);
     const uint32_t base = offset[blockIdx.x];
+    if (threadIdx.x < kPatchSlots / 32) used[threadIdx.x] = 0u;
+    if (threadIdx.x < 32) bank_use[threadIdx.x] = 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int k = 4 * threadIdx.x + r;
@@ -292,7 +305,51 @@ __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64
             node_start[base + u] = k;
             ++u;
         }
-        if (keys[k] != kNoKey) pos_of_slot[keys[k] & 1023u] = static_cast<uint16_t>(k);
+        if (keys[k] != kNoKey) {
+            // this sorted position's run: back to its head, forward to its end
+            int b = k;
+            while (!run_head(keys, b)) --b;
+            int e = k + 1;
+            while (e < kPatchSlots && keys[e] != kNoKey && !run_head(keys, e)) ++e;
+            const unsigned slot = static_cast<unsigned>(keys[k] & 1023u);
+            run_first[slot] = static_cast<uint16_t>(b);
+            run_len[slot] = static_cast<uint16_t>(e - b);
+        }
+    }
+    __syncthreads();
+    // the greedy choice, by the first wave: lanes examine candidate positions
+    // of the run in parallel, a wave minimum picks one, lane 0 records it
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (int h = 0; 32 * h < nel; ++h) {
+            const int hn = min(32, nel - 32 * h);
+            for (int a = 0; a < 4; ++a) {
+                for (int i = 0; i < hn; ++i) {
+                    const int slot = 4 * (32 * h + i) + a;
+                    const int rf = run_first[slot], rl = run_len[slot];
+                    uint32_t best = 0xffffffffu;
+                    for (int k = lane; k < rl; k += 64) {
+                        const int q = rf + k;
+                        if (!((used[q >> 5] >> (q & 31)) & 1u)) best = min(best, (bank_use[q & 31] << 16) | k);
+                    }
+                    for (int o = 32; o > 0; o >>= 1)
+                        best = min(best, static_cast<uint32_t>(__shfl_xor(static_cast<int>(best), o, 64)));
+                    if (lane == 0) {
+                        const int q = rf + static_cast<int>(best & 0xffffu);
+                        used[q >> 5] |= 1u << (q & 31);
+                        bank_use[q & 31] += 1u;
+                        pos_of_slot[slot] = static_cast<uint16_t>(q);
+                    }
+                    // only the first wave runs this loop: make lane 0's LDS
+                    // writes visible to the wave before the next pair
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+                if (lane < 32) bank_use[lane] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
     }
     __syncthreads();
     const int64_t s = first + threadIdx.x;
