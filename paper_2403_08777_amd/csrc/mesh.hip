@@ -259,74 +259,119 @@ __global__ __launch_bounds__(kThreads) void k_patch_count(const int4 *conn, int6
     if (threadIdx.x == 0) count[blockIdx.x] = total;
 }
 
-// Pass 2: for each patch write its distinct nodes (ascending), the start of
-// each node's run of slots in node-sorted order, and for every element the
-// positions of its four (element, vertex) slots.  An assembly workgroup
-// stores element contributions at those positions and then sums each node's
-// run: a deterministic in-LDS reduction without atomics.  Which position of
-// its node's run each (element, vertex) pair takes is free; it is chosen so
-// that the stores of one instruction -- vertex a of the 32 elements of a
-// half-wave, which the LDS serves together, a double's bank pair being its
-// slot modulo 32 -- fall into different banks where possible: greedily, half
-// -wave by half-wave and vertex by vertex, each pair takes the free position
-// of its run whose bank this instruction has used least (the lowest such
-// position on ties).  Patches with more than kMaxPatchNodes nodes are rejected
-// (from pass 1) on the host before this runs.
+// Pass 2: for each patch write its distinct nodes (ascending), where each
+// node's run of slots lies, and for every element the positions of its four
+// (element, vertex) slots.  An assembly workgroup stores element
+// contributions at those positions and then sums each node's run (one thread
+// per node, records ordered by decreasing run length): a deterministic
+// in-LDS reduction without atomics.  Where runs and positions lie is free;
+// both are chosen to spread the LDS banks (a double's bank pair is its slot
+// modulo 32, and the LDS serves the 32 lanes of a half-wave together):
+//  - runs are placed one after another, each time taking, among the runs not
+//    yet placed and in record order, the first whose half-wave of summing
+//    threads has no run starting at the current position modulo 32 yet, so
+//    that the run reads of a half-wave start in different banks;
+//  - each (element, vertex) pair takes the free position of its node's run
+//    whose bank the store instruction of its half-wave and vertex has used
+//    least (the lowest such position on ties), half-wave by half-wave and
+//    vertex by vertex.
+// node_start receives each run as first | length << 11.  Patches with more
+// than kMaxPatchNodes nodes are rejected (from pass 1) on the host before
+// this runs.
 __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64_t ne, int elems,
                                                           const uint32_t *offset, int32_t *nodes,
                                                           int32_t *node_start, ushort4 *elem_pos) {
     __shared__ uint64_t keys[kPatchSlots];
     __shared__ uint16_t pos_of_slot[kPatchSlots];
-    __shared__ uint16_t run_first[kPatchSlots];   // by element slot: its node's run [first, first + len)
-    __shared__ uint16_t run_len[kPatchSlots];
-    __shared__ uint32_t used[kPatchSlots / 32];    // run positions already taken
-    __shared__ uint32_t bank_use[32];              // stores per bank in the current instruction
+    __shared__ uint16_t run_of_slot[kPatchSlots];  // by element slot: its node's index in the patch
+    __shared__ uint16_t run_sorted[kMaxPatchNodes];  // per node: its first position in sorted order
+    __shared__ uint16_t run_len[kMaxPatchNodes];
+    __shared__ uint16_t run_place[kMaxPatchNodes];   // per node: first slot of its run
+    __shared__ uint8_t node_of_rank[kMaxPatchNodes]; // record order: longer runs first, then node order
+    __shared__ uint32_t used[kPatchSlots / 32];      // slots already taken
+    __shared__ uint32_t bank_use[32];                // stores per bank in the current instruction
+    __shared__ uint32_t left[kMaxPatchNodes / 32];   // record ranks not yet placed
+    __shared__ uint32_t half_used[kMaxPatchNodes / 32];  // per half-wave of records: starts taken modulo 32
     __shared__ uint32_t lds4[4];
     const int64_t first = static_cast<int64_t>(blockIdx.x) * elems;
     const int nel = static_cast<int>(min<int64_t>(elems, ne - first));
+    const int t = threadIdx.x;
     patch_sorted_pairs(conn, ne, first, elems, keys);
     bool head[4];
     uint32_t heads = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        head[r] = run_head(keys, 4 * threadIdx.x + r);
+        head[r] = run_head(keys, 4 * t + r);
         heads += head[r] ? 1u : 0u;
     }
-    uint32_t total;
-    uint32_t u = block_exclusive_scan_256(heads, lds4, &total);
-    const uint32_t base = offset[blockIdx.x];
-    if (threadIdx.x < kPatchSlots / 32) used[threadIdx.x] = 0u;
-    if (threadIdx.x < 32) bank_use[threadIdx.x] = 0u;
+    uint32_t nruns;
+    uint32_t u = block_exclusive_scan_256(heads, lds4, &nruns);
+    if (t < kPatchSlots / 32) used[t] = 0u;
+    if (t < 32) bank_use[t] = 0u;
+    if (t < kMaxPatchNodes / 32) {
+        const int n = static_cast<int>(nruns) - 32 * t;
+        left[t] = n >= 32 ? ~0u : (n > 0 ? (1u << n) - 1u : 0u);
+        half_used[t] = 0u;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int k = 4 * threadIdx.x + r;
+        const int k = 4 * t + r;
         if (head[r]) {
-            nodes[base + u] = static_cast<int32_t>(keys[k] >> 10);
-            node_start[base + u] = k;
-            ++u;
-        }
-        if (keys[k] != kNoKey) {
-            // this sorted position's run: back to its head, forward to its end
-            int b = k;
-            while (!run_head(keys, b)) --b;
             int e = k + 1;
             while (e < kPatchSlots && keys[e] != kNoKey && !run_head(keys, e)) ++e;
-            const unsigned slot = static_cast<unsigned>(keys[k] & 1023u);
-            run_first[slot] = static_cast<uint16_t>(b);
-            run_len[slot] = static_cast<uint16_t>(e - b);
+            nodes[offset[blockIdx.x] + u] = static_cast<int32_t>(keys[k] >> 10);
+            run_sorted[u] = static_cast<uint16_t>(k);
+            run_len[u] = static_cast<uint16_t>(e - k);
+            ++u;
         }
     }
     __syncthreads();
-    // the greedy choice, by the first wave: lanes examine candidate positions
-    // of the run in parallel, a wave minimum picks one, lane 0 records it
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
+    if (static_cast<uint32_t>(t) < nruns) {
+        const int mine = run_len[t];
+        int rank = 0;
+        for (int v = 0; v < static_cast<int>(nruns); ++v) {
+            const int lv = run_len[v];
+            rank += (lv > mine || (lv == mine && v < t)) ? 1 : 0;
+        }
+        node_of_rank[rank] = static_cast<uint8_t>(t);
+        for (int k = run_sorted[t]; k < run_sorted[t] + mine; ++k) run_of_slot[keys[k] & 1023u] = static_cast<uint16_t>(t);
+    }
+    __syncthreads();
+    // run placement and position choice by the first wave (only it runs
+    // these loops; the fences make lane 0's LDS writes visible to the wave)
+    if (t < 64) {
+        const int lane = t;
+        int cursor = 0;
+        for (uint32_t step = 0; step < nruns; ++step) {
+            const int res = cursor & 31;
+            int pick = -1, fallback = -1;
+#pragma unroll
+            for (int w = 0; w < kMaxPatchNodes / 64; ++w) {
+                const int rank = 64 * w + lane;
+                const bool here = ((left[rank >> 5] >> (rank & 31)) & 1u) != 0u;
+                const bool fits = here && !((half_used[rank >> 5] >> res) & 1u);
+                const uint64_t fb = __ballot(fits), lb = __ballot(here);
+                if (pick < 0 && fb) pick = 64 * w + __ffsll(static_cast<long long>(fb)) - 1;
+                if (fallback < 0 && lb) fallback = 64 * w + __ffsll(static_cast<long long>(lb)) - 1;
+            }
+            if (pick < 0) pick = fallback;
+            const int v = node_of_rank[pick];
+            if (lane == 0) {
+                left[pick >> 5] &= ~(1u << (pick & 31));
+                half_used[pick >> 5] |= 1u << res;
+                run_place[v] = static_cast<uint16_t>(cursor);
+            }
+            cursor += run_len[v];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int h = 0; 32 * h < nel; ++h) {
             const int hn = min(32, nel - 32 * h);
             for (int a = 0; a < 4; ++a) {
                 for (int i = 0; i < hn; ++i) {
                     const int slot = 4 * (32 * h + i) + a;
-                    const int rf = run_first[slot], rl = run_len[slot];
+                    const int v = run_of_slot[slot];
+                    const int rf = run_place[v], rl = run_len[v];
                     uint32_t best = 0xffffffffu;
                     for (int k = lane; k < rl; k += 64) {
                         const int q = rf + k;
@@ -340,8 +385,6 @@ __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64
                         bank_use[q & 31] += 1u;
                         pos_of_slot[slot] = static_cast<uint16_t>(q);
                     }
-                    // only the first wave runs this loop: make lane 0's LDS
-                    // writes visible to the wave before the next pair
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                 }
@@ -352,9 +395,11 @@ __global__ __launch_bounds__(kThreads) void k_patch_fill(const int4 *conn, int64
         }
     }
     __syncthreads();
-    const int64_t s = first + threadIdx.x;
-    if (threadIdx.x < elems && s < ne) {
-        const int b = 4 * threadIdx.x;
+    if (static_cast<uint32_t>(t) < nruns)
+        node_start[offset[blockIdx.x] + t] = static_cast<int32_t>(run_place[t]) | (static_cast<int32_t>(run_len[t]) << 11);
+    const int64_t s = first + t;
+    if (t < elems && s < ne) {
+        const int b = 4 * t;
         elem_pos[s] = make_ushort4(pos_of_slot[b], pos_of_slot[b + 1], pos_of_slot[b + 2], pos_of_slot[b + 3]);
     }
 }
@@ -392,8 +437,8 @@ __global__ __launch_bounds__(kThreads) void k_patch_color(const uint32_t *off, c
     for (int k = t; k < kColorLevels * kAdjWords; k += kThreads) (&adj[0][0])[k] = 0u;
     if (t < 64) used[t] = 0u;
     if (static_cast<uint32_t>(t) < cnt) {
-        const int sb = start[beg + t];
-        const int se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
+        const int sb = start[beg + t] & 0x7ff;
+        const int se = sb + (start[beg + t] >> 11);
         for (int k = sb; k < se; ++k) node_of_slot[k] = static_cast<uint8_t>(t);
     }
     __syncthreads();
@@ -478,12 +523,11 @@ __global__ __launch_bounds__(kThreads) void k_patch_pad(const uint32_t *off, con
     const int64_t p = blockIdx.x;
     const int t = threadIdx.x;
     const uint32_t beg = off[p], cnt = off[p + 1] - beg;
-    const int nel = static_cast<int>(min<int64_t>(elems, ne - p * elems));
     const bool real = static_cast<uint32_t>(t) < cnt;
     int sb = 0, se = 0;
     if (real) {
-        sb = start[beg + t];
-        se = (static_cast<uint32_t>(t) + 1 < cnt) ? start[beg + t + 1] : 4 * nel;
+        sb = start[beg + t] & 0x7ff;
+        se = sb + (start[beg + t] >> 11);
         len[t] = se - sb;
     }
     __syncthreads();
