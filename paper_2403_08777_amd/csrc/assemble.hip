@@ -620,12 +620,12 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
 
 // acc = sum of the slots [beg, end) of every component, in a fixed order.
 // FP64: chunks of four whose loads are independent (the run is read in
-// parallel, not one LDS round trip per slot); indices past the run are
-// clamped to its first slot and the values masked, so every read stays
-// inside the run.  FP32: blocks of four slots with no masking, then at most
-// one pair and one single slot (fewer instructions; in FP64 the masked form
-// measured faster).
-template <typename T, int NOUT, int KS>
+// parallel, not one LDS round trip per slot); a read past the run's end is
+// pointed at slot ZERO, which holds 0, so that every load is unconditional
+// and no value needs masking.  FP32: blocks of four slots, then at most one
+// pair and one single slot (fewer instructions; in FP64 these tails measured
+// slower, as they add dependent LDS round trips).
+template <typename T, int NOUT, int KS, int ZERO>
 __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[NOUT]) {
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
@@ -634,10 +634,9 @@ __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[N
             T v[4][NOUT];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bool in = k + j < end;
-                const int kk = in ? k + j : beg;
+                const int kk = k + j < end ? k + j : ZERO;
 #pragma unroll
-                for (int i = 0; i < NOUT; ++i) v[j][i] = in ? sval[i][kk] : T(0);
+                for (int i = 0; i < NOUT; ++i) v[j][i] = sval[i][kk];
             }
 #pragma unroll
             for (int i = 0; i < NOUT; ++i) acc[i] += (v[0][i] + v[1][i]) + (v[2][i] + v[3][i]);
@@ -678,10 +677,13 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     const uchar4 *__restrict__ elem_loc, const double *__restrict__ x,
     NodeFields<T> F, KParams<T> P, T *__restrict__ out) {
     using FL = Fields<MODE>;
+    // kS slots per component, then (FP64) a zero slot that reads past a run
+    // end are pointed at; rows padded to keep 16-byte alignment
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
+    constexpr int kSP = std::is_same<T, double>::value ? kS + 8 : kS;
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
     constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
-    constexpr size_t kSlotBytes = FL::NOUT * kS * sizeof(T);
+    constexpr size_t kSlotBytes = FL::NOUT * kSP * sizeof(T);
     // The FP64 forward and VJP read u_a (and lambda_a) from LDS where they use
     // them (twice each) instead of holding all four vertices in registers,
     // which keeps the forward at six waves per SIMD (five otherwise) and the
@@ -692,7 +694,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
-    T(*sval)[kS] = reinterpret_cast<T(*)[kS]>(smem);
+    T(*sval)[kSP] = reinterpret_cast<T(*)[kSP]>(smem);
 
     const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
     if (patch >= np) return;
@@ -765,6 +767,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) sval[i][sl[a]] = r[a][i];
     }
+    if (kSP > kS && t < FL::NOUT) sval[t][kS] = T(0);
     __syncthreads();
     // the slot run and the partial-sum position are loaded again (an L2 hit)
     // rather than kept live through the element arithmetic
@@ -776,7 +779,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     }
     if (has_node) {
         T acc[FL::NOUT];
-        run_sum<T, FL::NOUT, kS>(sval, s_beg, s_end, acc);
+        run_sum<T, FL::NOUT, kSP, kS>(sval, s_beg, s_end, acc);
         if (GATHER) {
 #pragma unroll
             for (int i = 0; i < FL::NOUT; ++i) out[FL::NOUT * static_cast<int64_t>(slot) + i] = acc[i];
