@@ -250,6 +250,36 @@ __device__ inline void eddy_d(const T (&G)[3][3], const EddyD<T> &ed, T (&D)[3][
     }
 }
 
+// M += s D with D = d mu_t / d G rebuilt from G as in eddy_d, the factor s
+// folded into the scalars (Smagorinsky: the symmetric sums G_ij + G_ji once
+// per pair, one fused multiply-add per entry).
+template <typename T, int EDDY>
+__device__ inline void add_scaled_eddy_d(const T (&G)[3][3], const EddyD<T> &ed, T s, T (&M)[3][3]) {
+    const T f = s * ed.k;
+    if (EDDY == kSmagorinsky) {
+        const T f2 = f + f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            M[i][i] += f2 * G[i][i];
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const T o = G[i][j] + G[j][i];
+                M[i][j] += f * o;
+                M[j][i] += f * o;
+            }
+        }
+    }
+    if (EDDY == kVreman) {
+        EddyD<T> e{f, ed.s2};
+        T D[3][3];
+        eddy_d<T, EDDY>(G, e, D);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) M[k][l] += D[k][l];
+    }
+}
+
 // Eddy viscosity mu_t of the element's constant velocity gradient G, with
 // filter width Delta = V^(1/3) and c = rho_c Delta^2; with WANT_D also
 // D = d mu_t / d G (0 where the model is not differentiable).
@@ -415,15 +445,7 @@ __device__ inline void element_vjp(const T (&gN)[4][3], T vol, LdU &&ldu, LdL &&
             M[k][k] += atw;
         }
     }
-    if (EDDY != kNoEddy) {
-        const T se = vol * phi;
-        T D[3][3];
-        eddy_d<T, EDDY>(G, ed, D);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) M[k][j] += se * D[k][j];
-    }
+    if (EDDY != kNoEddy) add_scaled_eddy_d<T, EDDY>(G, ed, vol * phi, M);
     const T at = (CONV == kGeneral) ? P.conv_a * (G[0][0] + G[1][1] + G[2][2]) : T(0);
     // (K^T w)_k = (G^T w)_k + conv_a tr(G) w_k + conv_b (G w)_k
     auto kt = [&](const T (&w)[3], T (&kw)[3]) {
