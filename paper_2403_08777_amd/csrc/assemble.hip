@@ -812,24 +812,29 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     }
 }
 
-// acc = sum of the partial sums [kb, ke), in a fixed order: pairs whose loads
-// are independent; an index past the run is clamped to its first entry (the
-// loop body runs only when the run is not empty) and the value masked.
+// acc = sum of the partial sums [kb, ke), in a fixed order: chunks of four
+// whose loads are all issued before any is used (most nodes have at most four
+// partial sums, so one round trip to memory); an index past the run is
+// clamped to its first entry (the loop body runs only when the run is not
+// empty) and the value masked.  Reference indices fit int32 (at most 2 Ne <
+// 2^30); the element offsets are formed in 64 bits.
 template <typename T, int NOUT>
-__device__ inline void gather_sum(const T *__restrict__ partial, int64_t kb, int64_t ke, T (&acc)[NOUT]) {
+__device__ inline void gather_sum(const T *__restrict__ partial, int kb, int ke, T (&acc)[NOUT]) {
 #pragma unroll
     for (int i = 0; i < NOUT; ++i) acc[i] = T(0);
-    for (int64_t k = kb; k < ke; k += 2) {
-        const bool in = k + 1 < ke;
-        const int64_t k1 = in ? k + 1 : kb;
-        T v0[NOUT], v1[NOUT];
+    for (int k = kb; k < ke; k += 4) {
+        T v[4][NOUT];
+        bool in[4];
 #pragma unroll
-        for (int i = 0; i < NOUT; ++i) {
-            v0[i] = partial[NOUT * k + i];
-            v1[i] = partial[NOUT * k1 + i];
+        for (int j = 0; j < 4; ++j) {
+            in[j] = k + j < ke;
+            const int kk = in[j] ? k + j : kb;
+#pragma unroll
+            for (int i = 0; i < NOUT; ++i) v[j][i] = partial[NOUT * static_cast<int64_t>(kk) + i];
         }
 #pragma unroll
-        for (int i = 0; i < NOUT; ++i) acc[i] += v0[i] + (in ? v1[i] : T(0));
+        for (int i = 0; i < NOUT; ++i)
+            acc[i] += (v[0][i] + (in[1] ? v[1][i] : T(0))) + ((in[2] ? v[2][i] : T(0)) + (in[3] ? v[3][i] : T(0)));
     }
 }
 
