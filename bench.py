@@ -42,7 +42,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FP64_PEAK_TFS = 78.6           # MI355X FP64 vector: 256 CUs x 2.4 GHz x 128 flop/cycle
 FP32_PEAK_TFS = 157.3          # MI355X FP32 vector (vendor; needs packed FP32 instructions)
-SIMDS = 256 * 4                # 256 compute units, 4 SIMDs each
+CUS = 256                      # compute units (one LDS each)
+SIMDS = CUS * 4                # 4 SIMDs per compute unit
 CLOCK_HZ = 2.4e9               # peak engine clock
 VALU_CYCLES = 4                # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
 
@@ -146,15 +147,20 @@ def resource_record():
 def kernel_evidence(ctr: dict | None, kernel: str, ms: float, scale_gbs: float | None):
     """Measured figures of one kernel from its counter entry and its live
     duration: HBM bytes and rate, executed FP64/FP32 flops and rate, how
-    busy the vector ALUs were, the LDS bank-conflict share and the L2 hit
-    rate.  None without a current counter record."""
+    busy the vector ALUs and the LDS were, the LDS bank-conflict share and
+    the L2 hit rate.  None without a current counter record.  Both busy
+    fractions are taken at the peak engine clock: cycles counted over cycles
+    available at 2.4 GHz (a lower clock under load would make the true
+    fractions larger).
+    SQ_LDS_IDX_ACTIVE counts the cycles a compute unit's LDS spends on indexed
+    operations (its bank-conflict cycles included), summed over all units."""
     if not ctr or kernel not in ctr:
         return None
     k = ctr[kernel]
     sec = ms * 1e-3
     pw = k.get("per_wave", {})
     waves = k.get("waves", 0.0)
-    out = {"hbm_bytes": k.get("hbm_bytes")}
+    out = {"hbm_bytes": k.get("hbm_bytes"), "waves": waves}
     if out["hbm_bytes"]:
         out["hbm_GBs"] = out["hbm_bytes"] / sec / 1e9
         out["hbm_frac_of_peak"] = out["hbm_GBs"] / HBM_PEAK_GBS
@@ -169,6 +175,8 @@ def kernel_evidence(ctr: dict | None, kernel: str, ms: float, scale_gbs: float |
         out["valu_busy"] = pw["SQ_INSTS_VALU"] * waves * VALU_CYCLES / (SIMDS * CLOCK_HZ * sec)
     if pw.get("SQ_LDS_IDX_ACTIVE"):
         out["lds_conflict_share"] = pw.get("SQ_LDS_BANK_CONFLICT", 0.0) / pw["SQ_LDS_IDX_ACTIVE"]
+        if waves:
+            out["lds_busy"] = pw["SQ_LDS_IDX_ACTIVE"] * waves / (CUS * CLOCK_HZ * sec)
         out["lds_bank_conflict_cycles_per_wave"] = pw.get("SQ_LDS_BANK_CONFLICT")
     if k.get("l2_hit_rate") is not None:
         out["l2_hit_rate"] = k["l2_hit_rate"]
@@ -178,18 +186,32 @@ def kernel_evidence(ctr: dict | None, kernel: str, ms: float, scale_gbs: float |
 def limiter(ev: dict | None) -> tuple:
     """(bound, verdict) from the measured evidence of the dominant kernel:
     the roof it is nearest to (VALU issue or HBM, against the Scale kernel's
-    attainable bandwidth), and whether it actually presses on it."""
+    attainable bandwidth), and whether it, or the LDS, actually presses on
+    its limit."""
     if not ev or "valu_busy" not in ev or ev.get("hbm_frac_of_scale") is None:
         return "alu", "no current counter record: bound by algorithmic intensity only"
     busy, hbm = ev["valu_busy"], ev["hbm_frac_of_scale"]
     bound = "alu" if busy >= hbm else "hbm"
+    if ev.get("waves") and ev["waves"] < SIMDS:
+        return bound, (f"latency: {ev['waves']:.0f} waves cannot fill the {SIMDS} SIMDs (VALU busy {busy:.2f}, "
+                       f"HBM {hbm:.2f} of the Scale bandwidth)")
     near = max(busy, hbm)
     if near >= 0.8:
         return bound, f"{'VALU issue' if bound == 'alu' else 'HBM bandwidth'} ({near:.2f} of it)"
+    if ev.get("lds_busy") is not None and ev["lds_busy"] >= 0.8:
+        return bound, (f"LDS throughput ({ev['lds_busy']:.2f} of it); VALU busy {busy:.2f}, "
+                       f"HBM {hbm:.2f} of the Scale bandwidth")
+    units = [("VALU", busy), ("HBM", hbm)]
+    if ev.get("lds_busy") is not None:
+        units.append(("LDS", ev["lds_busy"]))
+    top, top_frac = max(units, key=lambda u: u[1])
     cs = ev.get("lds_conflict_share")
-    extra = f", LDS bank-conflict share {cs:.2f}" if cs is not None else ""
-    return bound, (f"neither roof: VALU busy {busy:.2f}, HBM {hbm:.2f} of the Scale bandwidth{extra}; "
-                   "the rest is LDS and per-workgroup dependent-load latency")
+    lds = f"LDS busy {ev['lds_busy']:.2f}" if ev.get("lds_busy") is not None else "LDS busy unmeasured"
+    if cs is not None:
+        lds += f" (bank-conflict share {cs:.2f})"
+    return bound, (f"neither roof: {lds}, VALU busy {busy:.2f}, HBM {hbm:.2f} of the Scale bandwidth; "
+                   f"the busiest is {top} at {top_frac:.2f} and none is saturated: each workgroup's "
+                   "dependent loads, LDS phases and arithmetic, separated by barriers, overlap only in part")
 
 
 def parse():

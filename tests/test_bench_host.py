@@ -46,7 +46,7 @@ def _write(path, rec):
 
 
 def _ctr():
-    return {"k": {"waves": 1000.0, "hbm_bytes": 2.0e8, "f64_flops": 3.0e9, "f32_flops": 1.0e9, "l2_hit_rate": 0.7,
+    return {"k": {"waves": 2000.0, "hbm_bytes": 2.0e8, "f64_flops": 3.0e9, "f32_flops": 1.0e9, "l2_hit_rate": 0.7,
                   "per_wave": {"SQ_INSTS_VALU": 300.0, "SQ_LDS_IDX_ACTIVE": 400.0, "SQ_LDS_BANK_CONFLICT": 100.0}}}
 
 
@@ -68,10 +68,20 @@ def test_kernel_evidence_and_limiter():
     assert abs(ev["hbm_GBs"] - 2000.0) < 1e-9 and abs(ev["hbm_frac_of_scale"] - 0.4) < 1e-12
     assert abs(ev["executed_fp64_TFs"] - 30.0) < 1e-9
     assert abs(ev["executed_frac_of_valu_issue"] - 40.0 / bench.FP64_PEAK_TFS) < 1e-12
-    busy = 300.0 * 1000.0 * 4 / (1024 * 2.4e9 * 1e-4)
+    busy = 300.0 * 2000.0 * 4 / (1024 * 2.4e9 * 1e-4)
     assert abs(ev["valu_busy"] - busy) < 1e-12 and abs(ev["lds_conflict_share"] - 0.25) < 1e-12
+    # 400 LDS-active cycles a wave, 2000 waves, over 256 units x 2.4 GHz x 0.1 ms
+    assert abs(ev["lds_busy"] - 400.0 * 2000.0 / (256 * 2.4e9 * 1e-4)) < 1e-12
     bound, verdict = bench.limiter(ev)
-    assert bound == "hbm" and "neither roof" in verdict  # busy 0.0049 < HBM 0.4 < 0.8
+    assert bound == "hbm" and "neither roof" in verdict  # busy 0.0098 < HBM 0.4 < 0.8
+    assert "busiest is HBM at 0.40" in verdict and "bank-conflict share 0.25" in verdict
+    bound, verdict = bench.limiter({"valu_busy": 0.5, "hbm_frac_of_scale": 0.4, "lds_busy": 0.65,
+                                    "lds_conflict_share": 0.3})
+    assert bound == "alu" and "neither roof" in verdict and "busiest is LDS at 0.65" in verdict
+    bound, verdict = bench.limiter({"valu_busy": 0.5, "hbm_frac_of_scale": 0.4, "lds_busy": 0.85})
+    assert bound == "alu" and verdict.startswith("LDS throughput (0.85")
+    bound, verdict = bench.limiter({"valu_busy": 0.04, "hbm_frac_of_scale": 0.05, "waves": 384.0})
+    assert bound == "hbm" and verdict.startswith("latency: 384 waves cannot fill the 1024 SIMDs")
     bound, verdict = bench.limiter({"valu_busy": 0.9, "hbm_frac_of_scale": 0.3})
     assert bound == "alu" and "VALU issue" in verdict
     assert bench.kernel_evidence(None, "k", 0.1, 5000.0) is None
