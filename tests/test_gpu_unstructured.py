@@ -6,7 +6,9 @@ mesh preprocessing (Morton order, first-touch numbering, patch runs up to the
 highest valence, bank-aware run placement and node colouring) on the kind of
 irregular topology an LES mesh has.  FP64 forward, velocity and pressure VJPs
 and JVP against the oracle in every scatter strategy, with no eddy viscosity,
-Smagorinsky and Vreman; mixed precision on the mesh without its worst slivers."""
+Smagorinsky and Vreman; the other convective forms; the lumped volume and the
+explicit update with a Dirichlet mask; mixed precision on the mesh without
+its worst slivers."""
 
 import numpy as np
 import pytest
@@ -128,4 +130,72 @@ def test_unstructured_mixed(model):
     eg = oracle.rel_l2(g, oracle.vjp(pts, conn, u, lam, oprm))
     log(f"delaunay mixed {model} ({conn.shape[0]} tets): rhs {er:.2e}, grad {eg:.2e}")
     assert er <= TOL_MIXED and eg <= TOL_MIXED
+    mesh.close()
+
+
+@pytest.mark.parametrize("form", ["divergence", "skew", "rotational", "emac"])
+def test_unstructured_forms(form):
+    """The convective forms other than the advective one, FP64 forward, VJP and
+    JVP, with Smagorinsky, on every element."""
+    from paper_2403_08777_amd import api
+
+    conn = _delaunay()[1]
+    prm = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE, "smagorinsky", form)
+    oprm = oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE, "smagorinsky", form)
+    errs = _errors(conn, "auto", prm, oprm, f"delaunay ({form})")
+    assert all(v <= TOL64 for v in errs.values())
+
+
+def test_unstructured_update():
+    """Lumped volume and one explicit stage with a random Dirichlet mask, in
+    place and out of place, FP64."""
+    from paper_2403_08777_amd import api
+
+    pts, conn, u, p = _delaunay()[:4]
+    dev = torch.device("cuda")
+    dt = 1e-4
+    mesh = api.Mesh(torch.from_numpy(pts).to(dev), torch.from_numpy(conn).to(dev))
+    prm = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    oprm = oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    back = lambda t: mesh.from_mesh_order(t).cpu().numpy()
+    vl = back(mesh.lumped_volume())
+    vref = oracle.lumped_volume(pts, conn)
+    e_vol = float(np.max(np.abs(vl - vref) / vref))
+    mask_np = np.random.default_rng(5).integers(0, 8, pts.shape[0]).astype(np.uint8)
+    mask = mesh.to_mesh_order(torch.from_numpy(mask_np.astype(np.float64)).to(dev)).to(torch.uint8)
+    ut, pt = mesh.to_mesh_order(torch.from_numpy(u).to(dev)), mesh.to_mesh_order(torch.from_numpy(p).to(dev))
+    rhs = torch.empty_like(ut)
+    un = back(api.explicit_update(mesh, ut, pt, prm, dt, mask, rhs=rhs))
+    ref, ref_r = oracle.explicit_update(pts, conn, u, p, oprm, dt, mask_np)
+    fixed = np.stack([(mask_np >> i) & 1 for i in range(3)], axis=1).astype(bool)
+    assert np.array_equal(un[fixed], u[fixed])
+    e_inc = oracle.rel_l2(un - u, ref - u)
+    e_rhs = oracle.rel_l2(back(rhs), ref_r)
+    uu = ut.clone()
+    api.explicit_update(mesh, uu, pt, prm, dt, out=uu)
+    ref0, _ = oracle.explicit_update(pts, conn, u, p, oprm, dt)
+    e_inp = oracle.rel_l2(back(uu) - u, ref0 - u)
+    log(f"delaunay update: lumped max rel {e_vol:.2e}, increment {e_inc:.2e}, rhs {e_rhs:.2e}, in place {e_inp:.2e}")
+    assert e_vol <= 1e-14 and e_inc <= TOL64 and e_rhs <= TOL64 and e_inp <= TOL64
+    mesh.close()
+
+
+def test_unstructured_mixed_tangents():
+    """Mixed-precision JVP and pressure VJP on the sliver-filtered mesh."""
+    from paper_2403_08777_amd import api
+
+    pts, conn, u, p, lam, du, dp = _delaunay()
+    conn = conn[_quality(pts, conn) >= 1e-3]
+    dev = torch.device("cuda")
+    mesh = api.Mesh(torch.from_numpy(pts).to(dev), torch.from_numpy(conn).to(dev))
+    prm = api.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    oprm = oracle.Params(1.0, 1e-3, 0.1, synth.BODY_FORCE)
+    tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32))
+    back = lambda t: mesh.from_mesh_order(t).double().cpu().numpy()
+    jv = back(api.assemble_rhs_jvp(mesh, tm(u), tm(du), tm(dp), prm))
+    gp = back(api.assemble_rhs_vjp_p(mesh, tm(lam), prm))
+    ej = oracle.rel_l2(jv, oracle.jvp(pts, conn, u, p, du, dp, oprm))
+    ep = oracle.rel_l2(gp, oracle.vjp_p(pts, conn, lam))
+    log(f"delaunay mixed tangents ({conn.shape[0]} tets): jvp {ej:.2e}, vjp_p {ep:.2e}")
+    assert ej <= TOL_MIXED and ep <= TOL_MIXED
     mesh.close()
