@@ -231,6 +231,9 @@ def parse():
                     help="also time a plain device copy of 1 GiB (HBM bandwidth and counter calibration)")
     ap.add_argument("--blocks", type=int, default=0,
                     help="timed blocks of K steps (0: at least five and at least %d steps in all)" % MIN_TIMED_STEPS)
+    ap.add_argument("--unstructured", type=int, default=0, metavar="POINTS",
+                    help="also time FP64 and mixed forward + VJP on the Delaunay mesh of POINTS seeded "
+                         "uniform points (scipy; 1000000 points give 6.7 M tetrahedra)")
     ap.add_argument("--profile-run", action="store_true",
                     help="for profiler passes: only the listed configs, each timed briefly, no headline, "
                          "extras or oracle; prints one short JSON line")
@@ -580,7 +583,70 @@ def main():
     if copy_cal:
         result["copy_calibration"] = copy_cal
     result.update({k: v for k, v in extras.items() if k != "scatter"})
+    if args.unstructured > 0:
+        result["unstructured"] = unstructured_extra(args.unstructured, args, torch, api, synth)
     print(json.dumps(result), flush=True)
+
+
+def unstructured_extra(n_points, args, torch, api, synth):
+    """FP64 and mixed forward + velocity VJP (no eddy viscosity, mu = 1e-3) on
+    the Delaunay mesh of n_points seeded uniform points: median-block rate,
+    kernel durations, the mesh's layout figures and worst shape quality, and
+    (with the CPU baseline) the error against the oracle."""
+    t0 = time.perf_counter()
+    coords, conn = synth.delaunay_mesh(n_points)
+    gen_s = time.perf_counter() - t0
+    ne, nn = conn.shape[0], coords.shape[0]
+    d = coords[conn[:, 1:]] - coords[conn[:, :1]]
+    det = np.einsum("ij,ij->i", d[:, 0], np.cross(d[:, 1], d[:, 2]))
+    q_min = float(np.min(np.abs(det) / np.linalg.norm(d, axis=2).prod(axis=1)))
+    del d, det
+    u, p, lam = synth.unstructured_fields(coords)[:3]
+    dev = torch.device("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh = api.Mesh(torch.from_numpy(coords).to(dev), torch.from_numpy(conn).to(dev))
+    torch.cuda.synchronize()
+    out = {"workload": f"delaunay of {n_points} uniform points in the unit cube", "n_elems": ne, "n_nodes": nn,
+           "min_shape_quality": q_min, "mesh": mesh.info, "mesh_create_ms": (time.perf_counter() - t0) * 1e3,
+           "generate_s": gen_s, "mu": 1e-3, "smagorinsky_cs": 0.0}
+    log(f"[bench] unstructured: {ne} tets, {nn} nodes, generated in {gen_s:.1f} s, {mesh.info}")
+    prm = api.Params(1.0, 1e-3, 0.0, synth.BODY_FORCE)
+    refs = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oprm = oracle.Params(1.0, 1e-3, 0.0, synth.BODY_FORCE)
+        refs = (oracle.rhs(coords, conn, u, p, oprm), oracle.vjp(coords, conn, u, lam, oprm))
+    for name, dtype in (("fp64", torch.float64), ("mixed", torch.float32)):
+        tm = lambda a: mesh.to_mesh_order(torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype))
+        ut, pt, lt = tm(u), tm(p), tm(lam)
+        rhs, grad = torch.empty_like(ut), torch.empty_like(ut)
+        calls = [("fwd", lambda: api.assemble_rhs(mesh, ut, pt, prm, out=rhs)),
+                 ("vjp", lambda: api.assemble_rhs_vjp(mesh, ut, lt, prm, out=grad))]
+
+        def step():
+            for _, fn in calls:
+                fn()
+
+        blocks = time_blocks(torch, step, args.steps, args.warmup, args.blocks)
+        rec = {"elements_per_s": ne / (blocks["median_ms"] * 1e-3), "ms_per_step": blocks,
+               "kernels": time_phases(torch, api, calls, args.steps)}
+        if refs is not None:
+            import oracle
+
+            back = lambda t: mesh.from_mesh_order(t).double().cpu().numpy()
+            rec["rel_l2_vs_oracle"] = {"rhs": oracle.rel_l2(back(rhs), refs[0]),
+                                       "grad": oracle.rel_l2(back(grad), refs[1])}
+        out[name] = rec
+        log(f"[bench] unstructured {name}: {blocks['median_ms'] * 1e3:.1f} us/step, "
+            f"{rec['elements_per_s'] / 1e9:.2f} G elem/s; "
+            + ", ".join(f"{c}: {v['element_kernel_ms'] * 1e3:.1f} + {v['gather_kernel_ms'] * 1e3:.1f} us"
+                        for c, v in rec["kernels"].items())
+            + (f"; errors {rec['rel_l2_vs_oracle']}" if refs is not None else ""))
+        del ut, pt, lt, rhs, grad
+    mesh.close()
+    return out
 
 
 def profile_run(names, args, torch, api, synth, scale_gbs, res, copy_cal):

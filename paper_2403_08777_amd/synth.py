@@ -29,6 +29,13 @@ Recipe (every array is int32 / float64):
   U(-1e-2, 1e-2) noise per node and component from ``default_rng(3)`` (drawn in
   lattice order); pressure: sin 2pi x cos 2pi y;
 * adjoint: ``default_rng(4).standard_normal((Nn, 3))`` in user order.
+
+An unstructured mesh (``delaunay_mesh``) complements the cubes: the Delaunay
+tetrahedralisation (scipy's Qhull) of P points drawn uniformly in the unit cube
+by ``default_rng(seed)``, with nodes in drawing order.  Its node valence varies
+(4 to about 120, mean 27) and its worst elements are slivers, so it probes the
+mesh preprocessing and the patch layout on irregular topology; fields on it
+use ``unstructured_fields``.
 """
 
 from __future__ import annotations
@@ -145,6 +152,32 @@ def taylor_green(mesh: SynthMesh, noise: bool = True):
 def adjoint(n_nodes: int) -> np.ndarray:
     """Seeded standard-normal adjoint vector (Nn, 3), user order."""
     return np.random.default_rng(4).standard_normal((n_nodes, 3))
+
+
+def delaunay_mesh(n_points: int, seed: int = 1):
+    """Delaunay tetrahedralisation of n_points uniform points in the unit
+    cube: coords (n_points, 3) float64 and conn (Ne, 4) int32."""
+    if n_points < 5:
+        raise ValueError("n_points must be >= 5")
+    from scipy.spatial import Delaunay
+
+    pts = np.random.default_rng(seed).random((n_points, 3))
+    return pts, np.ascontiguousarray(Delaunay(pts).simplices.astype(np.int32))
+
+
+def unstructured_fields(coords: np.ndarray, seed: int = 2):
+    """Fields on an arbitrary node set, drawn in this order from
+    ``default_rng(seed)``: velocity u (the smooth field (sin 3y, cos 2z, xy)
+    plus normal noise of standard deviation 0.1), then standard-normal
+    pressure p, adjoint lambda, velocity tangent du and pressure tangent dp."""
+    rng = np.random.default_rng(seed)
+    x, y, z = (coords[:, c] for c in range(3))
+    u = np.stack([np.sin(3.0 * y), np.cos(2.0 * z), x * y], axis=1) + 0.1 * rng.standard_normal(coords.shape)
+    p = rng.standard_normal(coords.shape[0])
+    lam = rng.standard_normal(coords.shape)
+    du = rng.standard_normal(coords.shape)
+    dp = rng.standard_normal(coords.shape[0])
+    return u, p, lam, du, dp
 
 
 @dataclass(frozen=True)

@@ -77,3 +77,25 @@ def test_workloads_sizes():
     assert 6 * w["cube96_jit_perm"].n ** 3 == 5_308_416
     assert 6 * w["cube160_jit_perm_smag"].n ** 3 == 24_576_000
     assert (w["cube160_jit_perm_smag"].n + 1) ** 3 == 4_173_281
+
+
+def test_delaunay_mesh_and_fields():
+    coords, conn = synth.delaunay_mesh(500, seed=3)
+    assert coords.shape == (500, 3) and coords.dtype == np.float64
+    assert conn.dtype == np.int32 and conn.ndim == 2 and conn.shape[1] == 4 and conn.shape[0] > 500
+    assert conn.min() >= 0 and conn.max() < 500
+    assert all(len(set(row)) == 4 for row in conn.tolist())
+    d = coords[conn[:, 1:]] - coords[conn[:, :1]]
+    vol = np.abs(np.einsum("ij,ij->i", d[:, 0], np.cross(d[:, 1], d[:, 2]))) / 6.0
+    # a tetrahedralisation of the points' convex hull: positive volumes that
+    # add up to the hull's volume
+    from scipy.spatial import ConvexHull
+
+    assert vol.min() > 0.0 and abs(vol.sum() - ConvexHull(coords).volume) < 1e-12
+    c2, k2 = synth.delaunay_mesh(500, seed=3)
+    assert np.array_equal(coords, c2) and np.array_equal(conn, k2)
+    u, p, lam, du, dp = synth.unstructured_fields(coords, seed=5)
+    assert u.shape == lam.shape == du.shape == (500, 3) and p.shape == dp.shape == (500,)
+    assert np.array_equal(u, synth.unstructured_fields(coords, seed=5)[0])
+    with pytest.raises(ValueError):
+        synth.delaunay_mesh(4)
