@@ -134,7 +134,7 @@ typedef struct {
 } nsasm_params;
 
 typedef struct {
-    int32_t renumber;    /* 1 (default): sort elements along a Morton curve and
+    int32_t renumber;    /* 1 (default): sort elements along a Hilbert curve and
                             renumber nodes by first touch; 0: keep user order */
     int32_t scatter;     /* nsasm_scatter */
     int32_t patch_elems; /* elements per patch, 32..256 in steps of 32; 0 = 256,
@@ -157,7 +157,7 @@ typedef struct {
 
 /*
  * Build a mesh: validate the connectivity, then (renumber = 1) order elements
- * along a Morton curve of their centroids, renumber nodes in order of first
+ * along a Hilbert curve of their centroids, renumber nodes in order of first
  * use by that element order, and cut the element sequence into patches.
  * Locality of nodal gathers and scatters is what this buys (Sec. V-C:
  * indirect nodal accesses dominate once intermediates live in registers, and

@@ -30,7 +30,7 @@
 //
 // Scatter strategies:
 //   ATOMIC: one thread per element, 12 global atomic adds.
-//   PATCH:  one workgroup per patch of <= 256 consecutive (Morton-ordered)
+//   PATCH:  one workgroup per patch of <= 256 consecutive (Hilbert-ordered)
 //           elements; the patch's <= 256 distinct nodes are loaded once into
 //           LDS, element contributions are summed per node in LDS (slot runs,
 //           no LDS atomics), and each patch node gets one global atomic add

@@ -180,7 +180,7 @@ __device__ inline double tet_adjugate(const double (&xe)[4][3], double (&c1)[3],
 }
 
 // Workgroup b runs on XCD (b mod 8).  Give each XCD one contiguous run of
-// tiles so that tiles sharing nodes (neighbours in Morton order) share one L2.
+// tiles so that tiles sharing nodes (neighbours along the element curve) share one L2.
 // Valid only for grids built by xcd_grid(); returns a tile index that may be
 // >= the real tile count (the caller exits).
 __device__ inline int64_t xcd_tile(unsigned b, unsigned grid) {

@@ -1,4 +1,4 @@
-// Mesh preprocessing: validation, Morton element order, first-touch node
+// Mesh preprocessing: validation, Hilbert element order, first-touch node
 // renumbering, element patches; plus the user <-> mesh order helpers.
 //
 // The paper's kernels gather nodal values and scatter RHS entries through the
@@ -6,7 +6,7 @@
 // what remains (Sec. V-C); their reuse happens in the shared cache.  On a
 // chip with eight L2 caches (one per XCD) that reuse depends on the order of
 // elements and on node numbering, so the mesh is reordered here once:
-//   1. elements sorted along a Morton curve of their centroids;
+//   1. elements sorted along a Hilbert curve of their centroids;
 //   2. nodes renumbered in order of first use by that element sequence, so the
 //      nodes of consecutive elements have nearby ids (coalesced gathers);
 //   3. the sequence cut into patches of E consecutive elements; for each patch
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_bbox_final(const double *part, int
     if (threadIdx.x < 6) box[threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Spread the low 21 bits of v to every third bit (3-D Morton interleave).
+// Spread the low 21 bits of v to every third bit (the 3-D bit interleave).
 __device__ inline uint64_t spread_bits3(uint64_t v) {
     v &= 0x1fffffull;
     v = (v | (v << 32)) & 0x1f00000000ffffull;
@@ -116,7 +116,42 @@ __device__ inline uint64_t spread_bits3(uint64_t v) {
     return v;
 }
 
-// Morton key of each element's centroid (63 bits) and the degenerate-element check.
+// Index of cell (q0, q1, q2), 0 <= q < 2^21, along the 3-D Hilbert curve of
+// 2^21 cells per axis (63 bits), by Skilling's method (J. Skilling,
+// "Programming the Hilbert curve", AIP Conf. Proc. 707, 2004): the axes are
+// turned into the curve's transposed index level by level from the top
+// (reflect the lower bits of axis 0 where a coordinate's bit is set, else
+// exchange them between axis 0 and that axis), Gray-decoded, and the bits of
+// the three transposed words are interleaved, most significant level first,
+// axis 0 highest.  Consecutive indices are face-adjacent cells, so a run of
+// consecutive elements stays compact where a Morton curve would jump.
+__device__ inline uint64_t hilbert_key3(uint32_t q0, uint32_t q1, uint32_t q2) {
+    uint32_t X[3] = {q0, q1, q2};
+    constexpr uint32_t kTop = 1u << 20;
+    for (uint32_t Q = kTop; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = kTop; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    return (spread_bits3(X[0]) << 2) | (spread_bits3(X[1]) << 1) | spread_bits3(X[2]);
+}
+
+// Hilbert key of each element's centroid (63 bits) and the degenerate-element check.
 __global__ __launch_bounds__(kThreads) void k_element_keys(const double *x, const int32_t *conn,
                                                             int64_t ne, const double *box,
                                                             uint64_t *keys, int32_t *vals,
@@ -148,15 +183,15 @@ __global__ __launch_bounds__(kThreads) void k_element_keys(const double *x, cons
     }
     const double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
     const double scale = (ext > 0.0) ? 2097151.0 / ext : 0.0;
-    uint64_t key = 0;
+    uint32_t cell[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const double cen = 0.25 * (xe[0][i] + xe[1][i] + xe[2][i] + xe[3][i]);
         double q = (cen - box[i]) * scale;
         q = fmin(fmax(q, 0.0), 2097151.0);
-        key |= spread_bits3(static_cast<uint64_t>(q)) << i;
+        cell[i] = static_cast<uint32_t>(q);
     }
-    keys[e] = key;
+    keys[e] = hilbert_key3(cell[0], cell[1], cell[2]);
     vals[e] = static_cast<int32_t>(e);
 }
 

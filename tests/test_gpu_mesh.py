@@ -62,6 +62,34 @@ def test_patches_cover_elements():
     assert info["max_patch_nodes"] <= 256
 
 
+@pytest.mark.parametrize("kind", ["cube", "delaunay"])
+def test_element_order_is_hilbert(kind):
+    """The mesh's element sequence is the stable sort of the elements by the
+    Hilbert index of their centroid cell (tests/hilbert_ref.py, pinned on the
+    CPU), and the node numbering is the order of first use along it."""
+    from tests.hilbert_ref import element_order
+
+    if kind == "cube":
+        m = synth.cube_mesh(12, jitter=True, permute=True)
+        coords, conn = m.coords, m.conn
+    else:
+        coords, conn = synth.delaunay_mesh(20000, seed=7)
+    mesh = _mesh(coords, conn)
+    conn_mesh, elem = (t.cpu().numpy() for t in mesh.connectivity())
+    perm = mesh.permutation().cpu().numpy()
+    log(f"element order {kind}: {mesh.info}")
+    order = element_order(coords, conn)
+    assert np.array_equal(elem, order)
+    assert np.array_equal(conn_mesh, perm[conn[order]])
+    # first use: scanning the mesh connectivity row by row meets node ids in increasing order
+    flat = conn_mesh.reshape(-1)
+    first = np.full(len(perm), flat.size)
+    np.minimum.at(first, flat, np.arange(flat.size))
+    used = np.unique(flat)
+    assert np.array_equal(used[np.argsort(first[used])], np.arange(len(used)))
+    mesh.close()
+
+
 def test_relabel_invariance():
     """Relabelling user nodes, reordering elements and rotating each tet's local
     vertex order permutes the GPU result accordingly."""

@@ -2,7 +2,7 @@
 seeded random points in the unit cube (synth.delaunay_mesh) (268 K tetrahedra, node valence up to
 86, random node ids, slivers with |det J| / (|d1||d2||d3|) down to 3e-6).
 The cube meshes of the other tests are lattices; this one exercises the
-mesh preprocessing (Morton order, first-touch numbering, patch runs up to the
+mesh preprocessing (Hilbert order, first-touch numbering, patch runs up to the
 highest valence, bank-aware run placement and node colouring) on the kind of
 irregular topology an LES mesh has.  FP64 forward, velocity and pressure VJPs
 and JVP against the oracle in every scatter strategy, with no eddy viscosity,
