@@ -5,7 +5,7 @@ hot path: gather, geometry, gradients, element terms, scatter-add, adjoint) on
 the 96^3-cell jittered, relabelled cube (5,308,416 tets, 912,673 nodes),
 inputs resident in HBM in mesh order.  After W untimed steps the K-step
 timed region is repeated as back-to-back blocks of exactly K steps (at least
-five, and at least 400 steps in all) and ``ms_per_step`` is the median block;
+five, and at least 2000 steps in all) and ``ms_per_step`` is the median block;
 the first block is reported beside it.
 
 ``configs`` carries one record per workload of the method's measurement plan:
@@ -58,7 +58,8 @@ VALU_CYCLES = 4                # a wave64 VALU instruction occupies a 16-lane SI
 ALGORITHMIC_FLOPS = {("fwd", False): 528, ("fwd", True): 571, ("vjp", False): 827, ("vjp", True): 990}
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-MIN_TIMED_STEPS = 400          # the timed blocks cover at least this many steps
+MIN_TIMED_STEPS = 2000         # the timed blocks cover at least this many steps (the clocks
+                               # take tens of milliseconds to settle; short blocks need many)
 
 
 @dataclass(frozen=True)
