@@ -58,6 +58,7 @@ VALU_CYCLES = 4                # a wave64 VALU instruction occupies a 16-lane SI
 ALGORITHMIC_FLOPS = {("fwd", False): 528, ("fwd", True): 571, ("vjp", False): 827, ("vjp", True): 990}
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+PHASE_WARM_MS = 50.0           # untimed GPU work before the per-kernel timing
 MIN_TIMED_STEPS = 2000         # the timed blocks cover at least this many steps (the clocks
                                # take tens of milliseconds to settle; short blocks need many)
 
@@ -317,11 +318,12 @@ def time_blocks(torch, step, k: int, w: int, nblocks: int = 0) -> dict:
             "max_ms": max(per), "blocks": nblocks, "steps_per_block": k, "wall_ms": wall}
 
 
-def time_phases(torch, api, calls, k: int) -> dict:
+def time_phases(torch, api, calls, k: int, step_ms: float = 0.0) -> dict:
     """Each call's two kernels timed live inside a replica of the step,
-    repeated max(K, 100) times right after 20 untimed steps (no
-    synchronisation in between, so the clocks stay where the timed blocks
-    had them): nsasm_set_kernel_events has the library launch the element
+    repeated max(K, 100) times right after untimed steps that keep the GPU
+    busy for about 50 ms (at least 20; step_ms is the measured step time), with
+    no synchronisation in between, so that the clocks are back where the timed
+    blocks had them: nsasm_set_kernel_events has the library launch the element
     kernel and the gather kernel with HIP start/stop events that are recorded
     at the kernel's own start and end on the launch stream.  Mean and median
     duration of each kernel over the repetitions."""
@@ -332,7 +334,8 @@ def time_phases(torch, api, calls, k: int) -> dict:
         for e in row:
             e.record()
     torch.cuda.synchronize()
-    for _ in range(20):
+    warm = max(20, math.ceil(PHASE_WARM_MS / step_ms)) if step_ms > 0 else 20
+    for _ in range(warm):
         for _, fn in calls:
             fn()
     for row in rows:
@@ -433,7 +436,7 @@ def measure_config(cfg: Config, ld: Loaded, args, torch, api, scale_gbs, res, bl
 
     if blocks is None:
         blocks = time_blocks(torch, step, args.steps, args.warmup, args.blocks)
-    phases = time_phases(torch, api, calls, args.steps)
+    phases = time_phases(torch, api, calls, args.steps, blocks["median_ms"])
     ctr = counter_record(ld.wl.name)
     rec = {"workload": ld.wl.name, "n_elems": ld.ne, "n_nodes": ld.nn, "precision": cfg.precision,
            "form": cfg.form, "mu": ld.wl.mu, "smagorinsky_cs": ld.wl.cs, "mesh_create_ms": ld.create_ms,
@@ -632,7 +635,7 @@ def unstructured_extra(n_points, args, torch, api, synth):
 
         blocks = time_blocks(torch, step, args.steps, args.warmup, args.blocks)
         rec = {"elements_per_s": ne / (blocks["median_ms"] * 1e-3), "ms_per_step": blocks,
-               "kernels": time_phases(torch, api, calls, args.steps)}
+               "kernels": time_phases(torch, api, calls, args.steps, blocks["median_ms"])}
         if refs is not None:
             import oracle
 
