@@ -723,21 +723,21 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     const int t = threadIdx.x;
     const int64_t first = patch * static_cast<int64_t>(patch_elems);
     const int nel = static_cast<int>(min<int64_t>(patch_elems, ne - first));
-    ushort4 pos = make_ushort4(0, 0, 0, 0);
-    uchar4 loc = make_uchar4(0, 0, 0, 0);
-    if (t < nel) {
-        pos = elem_pos[first + t];
-        loc = elem_loc[first + t];
-    }
-    // every load of the patch's description is independent of the others
-    int64_t node = -1;
+    // Every load of the patch's description is independent of the others, so
+    // all three are issued at once, unconditionally (indices clamped into the
+    // patch: a patch has at least one element and its record stride is at
+    // least 8; lanes beyond them discard what they read).  The record comes
+    // first, as the node loads depend on it, and the element tables stay
+    // packed words until after the node staging, so that waiting for the
+    // record does not wait for them: unpacked at the load, they cost every
+    // workgroup one more memory round trip before its node loads could start.
+    const int2 rec = patch_rec[patch * stride + min(t, stride - 1)];
+    const int64_t te = first + min(t, nel - 1);
+    const uint2 pos_w = reinterpret_cast<const uint2 *>(elem_pos)[te];   // four 16-bit slot positions
+    const uint32_t loc_w = reinterpret_cast<const uint32_t *>(elem_loc)[te];  // four 8-bit LDS positions
     int32_t slot = 0, s_beg = 0, s_end = 0;
-    int lp = 0;  // the node's position in the LDS node arrays
-    if (t < stride) {
-        const int2 rec = patch_rec[patch * stride + t];
-        node = rec.x;
-        lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);
-    }
+    const int64_t node = t < stride ? rec.x : -1;
+    const int lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);  // the node's LDS position
     const bool has_node = node >= 0;
     if (has_node) {
 #pragma unroll
@@ -751,9 +751,9 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     __syncthreads();
 
     T r[4][3];
-    const int sl[4] = {pos.x, pos.y, pos.z, pos.w};
     if (t < nel) {
-        const int la[4] = {loc.x, loc.y, loc.z, loc.w};
+        const int la[4] = {static_cast<int>(loc_w & 0xffu), static_cast<int>((loc_w >> 8) & 0xffu),
+                           static_cast<int>((loc_w >> 16) & 0xffu), static_cast<int>(loc_w >> 24)};
         double xe[4][3];
         T ea[4][3] = {}, eb[4][3] = {}, ec[4] = {};
 #pragma unroll
@@ -784,6 +784,8 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     }
     __syncthreads();  // node data is dead from here on; its bytes become slots
     if (t < nel) {
+        const int sl[4] = {static_cast<int>(pos_w.x & 0xffffu), static_cast<int>(pos_w.x >> 16),
+                           static_cast<int>(pos_w.y & 0xffffu), static_cast<int>(pos_w.y >> 16)};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -791,14 +793,12 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     }
     if (kSP > kS && t < FL::NOUT) sval[t][kS] = T(0);
     __syncthreads();
-    // the slot run and the partial-sum position are loaded again (an L2 hit)
-    // rather than kept live through the element arithmetic
-    if (has_node) {
-        const int32_t ry = patch_rec[patch * stride + t].y;
-        s_beg = ry & 0x7ff;
-        s_end = (ry >> 11) & 0x7ff;
-        if (GATHER) slot = patch_ref[patch * stride + t];
-    }
+    // the slot run comes from the record word loaded at the start; the
+    // partial-sum position is loaded now (an L2 hit) and first used after
+    // the run reduction, which hides its latency
+    if (GATHER && has_node) slot = patch_ref[patch * stride + t];
+    s_beg = rec.y & 0x7ff;
+    s_end = (rec.y >> 11) & 0x7ff;
     if (has_node) {
         T acc[FL::NOUT];
         run_sum<T, FL::NOUT, kSP, kS>(sval, s_beg, s_end, acc);
