@@ -692,8 +692,16 @@ __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[N
 // sums in a fixed order.  GATHER = false adds each node sum to `out` with a
 // global atomic; GATHER = true stores it to the node-major partial-sum buffer
 // (position patch_ref of the record), for k_gather_partials.
+// Minimum waves per SIMD the register allocator is held to: the FP64 forward
+// without eddy viscosity or with Smagorinsky's fits six (its LDS allows six
+// workgroups per CU) without spilling; Vreman's would spill, and for every
+// other variant the compiler chooses.
+template <typename T, int EDDY, int MODE>
+constexpr int kPatchMinWaves =
+    (std::is_same<T, double>::value && MODE == kForward && EDDY != kVreman) ? 6 : 1;
+
 template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
-__global__ __launch_bounds__(kThreads) void k_assemble_patch(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatchMinWaves<T, EDDY, MODE>))) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, int32_t stride, const int2 *__restrict__ patch_rec,
     const int32_t *__restrict__ patch_ref, const ushort4 *__restrict__ elem_pos,
     const uchar4 *__restrict__ elem_loc, const double *__restrict__ x,
@@ -740,13 +748,25 @@ __global__ __launch_bounds__(kThreads) void k_assemble_patch(
     const int lp = static_cast<int>(static_cast<uint32_t>(rec.y) >> 22);  // the node's LDS position
     const bool has_node = node >= 0;
     if (has_node) {
+        // every load of the node before the first LDS store, so that they
+        // form one round trip (the scalar field's null check would otherwise
+        // hold its load back until the others had been stored)
+        double xv[3];
+        T av[3] = {}, bv[3] = {}, cv = T(0);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            sx[i][lp] = x[3 * node + i];
-            if (FL::NA) sf[i][lp] = F.fa[3 * node + i];
-            if (FL::NB) sf[FL::NA + i][lp] = F.fb[3 * node + i];
+            xv[i] = x[3 * node + i];
+            if (FL::NA) av[i] = F.fa[3 * node + i];
+            if (FL::NB) bv[i] = F.fb[3 * node + i];
         }
-        if (FL::NC) sf[FL::NA + FL::NB][lp] = F.fc ? F.fc[node] : T(0);
+        if (FL::NC && F.fc) cv = F.fc[node];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sx[i][lp] = xv[i];
+            if (FL::NA) sf[i][lp] = av[i];
+            if (FL::NB) sf[FL::NA + i][lp] = bv[i];
+        }
+        if (FL::NC) sf[FL::NA + FL::NB][lp] = cv;
     }
     __syncthreads();
 
