@@ -121,16 +121,20 @@ __device__ inline float quotient(float a, float b) { return a * __builtin_amdgcn
 
 // ----------------------------------------------------------- element math
 
-// Shape-function gradients and volume, always in FP64.
+// Shape-function gradients and volume, always in FP64.  1/det is the
+// hardware reciprocal estimate refined by NEWTON Newton-Raphson steps, each
+// of which squares the relative error: two are enough for full double
+// precision (the finite, non-zero determinants a validated mesh has), as
+// they are for the library's own FP64 division, so the estimate is good to
+// about 2^-13.5; the mixed path rounds the gradients to FP32 afterwards, and
+// after one step (error below 2^-26) it takes only that one.
+template <int NEWTON = 2>
 __device__ inline void tet_geometry(const double (&xe)[4][3], double (&gN)[4][3], double &vol) {
     double c1[3], c2[3], c3[3], d1[3];
     const double det = tet_adjugate(xe, c1, c2, c3, d1);
-    // 1/det: hardware reciprocal estimate refined by two Newton-Raphson steps
-    // (each squares the relative error), enough for full double precision for
-    // the finite, non-zero determinants a validated mesh has.
     double inv = __builtin_amdgcn_rcp(det);
-    inv = fma(inv, fma(-det, inv, 1.0), inv);
-    inv = fma(inv, fma(-det, inv, 1.0), inv);
+#pragma unroll
+    for (int k = 0; k < NEWTON; ++k) inv = fma(inv, fma(-det, inv, 1.0), inv);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         gN[1][i] = c1[i] * inv;
@@ -581,14 +585,24 @@ __device__ inline void element_op(const T (&gN)[4][3], T vol, const T (&ea)[4][3
     }
 }
 
+// The geometry in the field precision.  In FP32, grad N_0 = -(grad N_1 +
+// grad N_2 + grad N_3) is formed from the rounded gradients (three
+// conversions fewer; its FP64 value is then never computed).
 template <typename T>
 __device__ inline void to_field(const double (&g64)[4][3], double vol64, T (&gN)[4][3], T &vol) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 1; a < 4; ++a)
 #pragma unroll
         for (int i = 0; i < 3; ++i) gN[a][i] = static_cast<T>(g64[a][i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        gN[0][i] = std::is_same<T, double>::value ? static_cast<T>(g64[0][i]) : -(gN[1][i] + gN[2][i] + gN[3][i]);
     vol = static_cast<T>(vol64);
 }
+
+// Newton steps of the reciprocal in tet_geometry for field type T.
+template <typename T>
+constexpr int kGeomNewton = std::is_same<T, double>::value ? 2 : 1;
 
 // ------------------------------------------------------------- kernels
 
@@ -631,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble_atomic(int64_t ne, const 
         if (FL::NC) ec[a] = F.fc ? F.fc[ids[a]] : T(0);
     }
     double g64[4][3], vol64;
-    tet_geometry(xe, g64, vol64);
+    tet_geometry<kGeomNewton<T>>(xe, g64, vol64);
     T gN[4][3], vol;
     to_field(g64, vol64, gN, vol);
     element_op<T, EDDY, CONV, MODE>(gN, vol, ea, eb, ec, P, [&](int a, const T (&r)[3]) {
@@ -717,10 +731,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
     // The FP64 forward and VJP read u_a (and lambda_a) from LDS where they use
     // them (twice each) instead of holding all four vertices in registers,
     // which keeps the forward at six waves per SIMD (five otherwise) and the
-    // VJP at five (four otherwise).  In FP32 the kernel already runs eight
-    // waves and the extra LDS reads would only cost.
+    // VJP at five (four otherwise).  The FP32 kernels hold them in registers
+    // and still run seven or eight waves, except the VJP of a general
+    // convective form with an eddy model, which would lose a wave.
     constexpr bool kLds = ((MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value) ||
-                          (MODE == kVjp && EDDY != kNoEddy);
+                          (MODE == kVjp && EDDY != kNoEddy && CONV == kGeneral);
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
     double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
     T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
@@ -787,7 +802,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
             if (FL::NC) ec[a] = sf[FL::NA + FL::NB][la[a]];
         }
         double g64[4][3], vol64;
-        tet_geometry(xe, g64, vol64);
+        tet_geometry<kGeomNewton<T>>(xe, g64, vol64);
         T gN[4][3], vol;
         to_field(g64, vol64, gN, vol);
         auto sink = [&](int a, const T (&v)[3]) {
