@@ -708,14 +708,17 @@ __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[N
 // (position patch_ref of the record), for k_gather_partials.
 // Minimum waves per SIMD the register allocator is held to: the FP64 forward
 // without eddy viscosity or with Smagorinsky's fits six (its LDS allows six
-// workgroups per CU) without spilling; Vreman's would spill, and for every
-// other variant the compiler chooses.
-template <typename T, int EDDY, int MODE>
+// workgroups per CU), and the FP64 advective VJP without eddy viscosity five,
+// without spilling; the other variants would spill (Vreman's forward, the
+// general-form VJP) or need no hint, and the compiler chooses.
+template <typename T, int EDDY, int CONV, int MODE>
 constexpr int kPatchMinWaves =
-    (std::is_same<T, double>::value && MODE == kForward && EDDY != kVreman) ? 6 : 1;
+    (std::is_same<T, double>::value && MODE == kForward && EDDY != kVreman)                            ? 6
+    : (std::is_same<T, double>::value && MODE == kVjp && EDDY == kNoEddy && CONV == kAdvective) ? 5
+                                                                                                    : 1;
 
 template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatchMinWaves<T, EDDY, MODE>))) void k_assemble_patch(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatchMinWaves<T, EDDY, CONV, MODE>))) void k_assemble_patch(
     int64_t ne, int64_t np, int32_t patch_elems, int32_t stride, const int2 *__restrict__ patch_rec,
     const int32_t *__restrict__ patch_ref, const ushort4 *__restrict__ elem_pos,
     const uchar4 *__restrict__ elem_loc, const double *__restrict__ x,
@@ -726,7 +729,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
     constexpr int kSP = std::is_same<T, double>::value ? kS + 8 : kS;
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
-    constexpr size_t kNodeBytes = 3 * kN * sizeof(double) + kNF * kN * sizeof(T);
+    // The FP32 forward and the FP64 forward and advective VJP without eddy
+    // viscosity pad each row of the node arrays by 32 floats / 16 doubles, so
+    // that the fields of one node lie in different LDS bank pairs: with
+    // 256-entry rows the compiler pairs the reads of two fields of a vertex
+    // into one instruction whose two addresses share a bank pair.  Measured
+    // at 96^3 / 160^3: FP64 forward 66.8 -> 63.9 us, FP64 VJP 81.2 -> 78.9 us
+    // (held to five waves, see kPatchMinWaves), FP32 forward -2 %; the FP64
+    // Smagorinsky forward and the FP32 VJPs measured slower with it
+    // (instruction mix, registers) and keep 256-entry rows.
+    constexpr bool kPadRows =
+        (MODE == kForward && (!std::is_same<T, double>::value || EDDY == kNoEddy)) ||
+        (MODE == kVjp && std::is_same<T, double>::value && EDDY == kNoEddy && CONV == kAdvective);
+    constexpr int kNR = kN + (kPadRows ? (std::is_same<T, double>::value ? 16 : 32) : 0);
+    constexpr size_t kNodeBytes = 3 * kNR * sizeof(double) + kNF * kNR * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kSP * sizeof(T);
     // The FP64 forward and VJP read u_a (and lambda_a) from LDS where they use
     // them (twice each) instead of holding all four vertices in registers,
@@ -737,8 +753,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
     constexpr bool kLds = ((MODE == kForward || MODE == kVjp) && std::is_same<T, double>::value) ||
                           (MODE == kVjp && EDDY != kNoEddy && CONV == kGeneral);
     __shared__ __align__(16) unsigned char smem[kNodeBytes > kSlotBytes ? kNodeBytes : kSlotBytes];
-    double(*sx)[kN] = reinterpret_cast<double(*)[kN]>(smem);
-    T(*sf)[kN] = reinterpret_cast<T(*)[kN]>(smem + 3 * kN * sizeof(double));  // A, then B, then C
+    double(*sx)[kNR] = reinterpret_cast<double(*)[kNR]>(smem);
+    T(*sf)[kNR] = reinterpret_cast<T(*)[kNR]>(smem + 3 * kNR * sizeof(double));  // A, then B, then C
     T(*sval)[kSP] = reinterpret_cast<T(*)[kSP]>(smem);
 
     const int64_t patch = xcd_tile(blockIdx.x, gridDim.x);
