@@ -91,15 +91,28 @@ __device__ inline void global_add(float *p, float v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Delta^2 = V^(2/3), the squared filter width of the eddy viscosity.  FP64:
-// the device library's cube root.  FP32 (the mixed path): y = V^(-1/3) from
-// the hardware base-2 logarithm and exponential, refined by one Newton step
-// y <- y (4 - V y^3) / 3 (the estimate's error, about 1e-6 for small V, is
-// squared), then V^(2/3) = V y.  Volumes below 2^-100 are scaled by 2^96
-// first (2^64 after the power), so that the logarithm never sees a denormal.
+// Delta^2 = V^(2/3), the squared filter width of the eddy viscosity, from an
+// estimate y of V^(-1/3) built with the hardware base-2 logarithm and
+// exponential, then V^(2/3) = V y.
+// FP64: V = w 2^(3q), q = (21846 e) >> 16 for V's binary exponent e (e / 3
+// rounded down, or one below it for the negative multiples of 3), so that w
+// lies in [1/2, 8) and y estimates w^(-1/3) to about 2^-22; one step of the
+// binomial series (1 - r)^(-1/3) = 1 + h + 2 h^2 + 14 h^3 / 3 + ...,
+// r = 1 - w y^3, h = r / 3, taken to second order then leaves about
+// 14 |h|^3 / 3 with |h| about 2^-22, far below rounding;
+// V^(2/3) = (w y) 2^(2q).
+// FP32 (the mixed path): y <- y (4 - V y^3) / 3, one Newton step (the
+// estimate's error, about 1e-6 for small V, is squared).  Volumes below
+// 2^-100 are scaled by 2^96 first (2^64 after the power), so that the
+// logarithm never sees a denormal.
 __device__ inline double filter_width_sq(double v) {
-    const double d = cbrt(v);
-    return d * d;
+    const int q = __mul24(__builtin_amdgcn_frexp_exp(v), 21846) >> 16;
+    const double w = ldexp(v, -3 * q);
+    double y = static_cast<double>(
+        __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(static_cast<float>(w)) * (-1.0f / 3.0f)));
+    const double h = fma(-w, y * y * y, 1.0) * (1.0 / 3.0);
+    y = fma(y, h * fma(h, 2.0, 1.0), y);
+    return ldexp(w * y, 2 * q);
 }
 __device__ inline float filter_width_sq(float v) {
     const bool tiny = v < 0x1p-100f;
@@ -110,13 +123,37 @@ __device__ inline float filter_width_sq(float v) {
     return tiny ? d2 * 0x1p-64f : d2;
 }
 
+// 1 / sqrt(x) in FP64 for x > 0 (normal or not): x = w 4^p with
+// p = floor(e/2) for x's binary exponent e, so that w lies in [1/2, 2); the
+// hardware FP32 reciprocal square root of w (about 2^-22 after the
+// conversions) and one step of the binomial series
+// (1 - t)^(-1/2) = 1 + h + 3 h^2 / 2 + 5 h^3 / 2 + ..., t = 1 - w y^2,
+// h = t / 2, to second order (leaving about 5 |h|^3 / 2, |h| about 2^-22);
+// then 1 / sqrt(x) = y 2^-p.
+__device__ inline double inv_root(double x) {
+    const int p = __builtin_amdgcn_frexp_exp(x) >> 1;
+    const double w = ldexp(x, -2 * p);
+    double y = static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(w)));
+    const double h = fma(-w, y * y, 1.0) * 0.5;
+    y = fma(y, h * fma(h, 1.5, 1.0), y);
+    return ldexp(y, -p);
+}
+
 // sqrt: correctly rounded in FP64; the hardware square root (1 ulp) in FP32.
 __device__ inline double root(double v) { return sqrt(v); }
 __device__ inline float root(float v) { return __builtin_amdgcn_sqrtf(v); }
 
-// a / b: IEEE division in FP64; in FP32 (the mixed path, whose error is
-// measured, not bounded) the hardware reciprocal (1 ulp) times a.
-__device__ inline double quotient(double a, double b) { return a / b; }
+// a / b for the eddy model's ratios of normal, finite operands: a times 1/b.
+// FP64: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (as for 1/det J), within about one ulp, so the ratio is within two.  FP32
+// (the mixed path, whose error is measured, not bounded): the hardware
+// reciprocal (1 ulp).
+__device__ inline double quotient(double a, double b) {
+    double inv = __builtin_amdgcn_rcp(b);
+    inv = fma(inv, fma(-b, inv, 1.0), inv);
+    inv = fma(inv, fma(-b, inv, 1.0), inv);
+    return a * inv;
+}
 __device__ inline float quotient(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // ----------------------------------------------------------- element math
@@ -209,9 +246,18 @@ __device__ inline T eddy_viscosity_k(const T (&G)[3][3], T vol, T rho_c, EddyD<T
                 ss += o * o;
             }
         }
-        const T smag = root(ss);
-        ed.k = (smag > T(0)) ? quotient(c, smag) : T(0);
-        return c * smag;
+        if constexpr (std::is_same<T, double>::value) {
+            // |S| = ss / sqrt(ss) and c / |S| = c / sqrt(ss): one reciprocal
+            // square root, no division; 0 for a uniform velocity (ss = 0)
+            const bool live = ss > 0.0;
+            const double ir = inv_root(ss);
+            ed.k = live ? c * ir : 0.0;
+            return live ? c * (ss * ir) : 0.0;
+        } else {
+            const T smag = root(ss);
+            ed.k = (smag > T(0)) ? quotient(c, smag) : T(0);
+            return c * smag;
+        }
     }
     T C[3][3];
     cofactors(G, C);
