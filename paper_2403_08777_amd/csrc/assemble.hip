@@ -123,7 +123,8 @@ __device__ inline float filter_width_sq(float v) {
     return tiny ? d2 * 0x1p-64f : d2;
 }
 
-// 1 / sqrt(x) in FP64 for x > 0 (normal or not): x = w 4^p with
+// 1 / sqrt(x) for x > 0.  FP32: the hardware reciprocal square root (1 ulp).
+// FP64 (normal or not): x = w 4^p with
 // p = floor(e/2) for x's binary exponent e, so that w lies in [1/2, 2); the
 // hardware FP32 reciprocal square root of w (about 2^-22 after the
 // conversions) and one step of the binomial series
@@ -138,9 +139,9 @@ __device__ inline double inv_root(double x) {
     y = fma(y, h * fma(h, 1.5, 1.0), y);
     return ldexp(y, -p);
 }
+__device__ inline float inv_root(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// sqrt: correctly rounded in FP64; the hardware square root (1 ulp) in FP32.
-__device__ inline double root(double v) { return sqrt(v); }
+// sqrt in FP32: the hardware square root (1 ulp).
 __device__ inline float root(float v) { return __builtin_amdgcn_sqrtf(v); }
 
 // a / b for the eddy model's ratios of normal, finite operands: a times 1/b.
@@ -208,17 +209,22 @@ __device__ inline void cofactors(const T (&G)[3][3], T (&C)[3][3]) {
         }
 }
 
-// d mu_t / d G is rebuilt from G where it is used (eddy_d), from two scalars,
-// so that its nine entries need not stay live:
+// d mu_t / d G is rebuilt from G where it is used (eddy_d), from a few
+// scalars, so that its nine entries need not stay live:
 //   Smagorinsky D_ij = k (G_ij + G_ji)              (k = c / |S|),
-//   Vreman      D_ij = k (N_ij - s2 G_ij)            (k = c / (A s), s2 = s^2),
+//   Vreman      D_ij = k (N_ij / A - s2 G_ij)       (k = c / s, s2 = s^2 / A),
 // with N = (tr(P) I - P) G, P = G G^T, evaluated as the cofactor contraction
 // N_kl = G_{k1 l1} C_{k2 l2} - G_{k1 l2} C_{k2 l1} - G_{k2 l1} C_{k1 l2} + G_{k2 l2} C_{k1 l1}
-// (k1 = k+1, k2 = k+2 mod 3; C the cofactors of G).
+// (k1 = k+1, k2 = k+2 mod 3; C the cofactors of G), N / A from the cofactors
+// scaled by ia = 1 / A.  Dividing both terms by A, rather than the factor
+// k (which would then be c / (A s)), keeps every intermediate within a few
+// powers of the element size h (c / (A s) grows as h^5 and its product with
+// the VJP's weights as h^7, beyond the double range some 2^140 from unit scale).
 template <typename T>
 struct EddyD {
     T k;
     T s2;
+    T ia;
 };
 
 // Vreman's B_beta / Delta^4 = e2(P) equals, by the Cauchy-Binet formula, the
@@ -231,6 +237,7 @@ template <typename T, int EDDY>
 __device__ inline T eddy_viscosity_k(const T (&G)[3][3], T vol, T rho_c, EddyD<T> &ed) {
     ed.k = T(0);
     ed.s2 = T(0);
+    ed.ia = T(0);
     if (EDDY == kNoEddy) return T(0);
     const T c = rho_c * filter_width_sq(vol);
     if (EDDY == kSmagorinsky) {
@@ -269,11 +276,16 @@ __device__ inline T eddy_viscosity_k(const T (&G)[3][3], T vol, T rho_c, EddyD<T
             A += G[i][j] * G[i][j];
             B += C[i][j] * C[i][j];
         }
+    // s = sqrt(B / A) and c / s from one reciprocal square root; 0 where the
+    // model is (G of rank one or zero)
     const bool live = (A > T(0)) && (B > T(0));
-    const T s = live ? root(quotient(B, A)) : T(0);
-    ed.k = live ? quotient(c, A * s) : T(0);
-    ed.s2 = s * s;
-    return c * s;
+    const T ia = live ? quotient(T(1), A) : T(0);
+    const T q = B * ia;
+    const T r = inv_root(q);
+    ed.k = live ? c * r : T(0);
+    ed.s2 = q * ia;
+    ed.ia = ia;
+    return live ? c * (q * r) : T(0);
 }
 
 // All of D = d mu_t / d G from G and the scalars of eddy_viscosity_k.
@@ -288,6 +300,10 @@ __device__ inline void eddy_d(const T (&G)[3][3], const EddyD<T> &ed, T (&D)[3][
     if (EDDY == kVreman) {
         T C[3][3];
         cofactors(G, C);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) C[i][j] *= ed.ia;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -320,7 +336,7 @@ __device__ inline void add_scaled_eddy_d(const T (&G)[3][3], const EddyD<T> &ed,
         }
     }
     if (EDDY == kVreman) {
-        EddyD<T> e{f, ed.s2};
+        EddyD<T> e{f, ed.s2, ed.ia};
         T D[3][3];
         eddy_d<T, EDDY>(G, e, D);
 #pragma unroll
