@@ -770,13 +770,14 @@ __device__ inline void run_sum(const T (*sval)[KS], int beg, int end, T (&acc)[N
 // (position patch_ref of the record), for k_gather_partials.
 // Minimum waves per SIMD the register allocator is held to: every FP64
 // forward fits six (its LDS allows six workgroups per CU) and the FP64
-// advective VJP without eddy viscosity five, without spilling; the other
-// FP64 VJPs would spill at five (the Smagorinsky one by 12 bytes per lane)
-// and the FP32 kernels need no hint, so the compiler chooses.
+// advective VJP without eddy viscosity five, without spilling; the advective
+// Smagorinsky VJP runs five too, spilling 12 bytes per lane (2-4 % faster
+// than four waves without spills); the other FP64 VJPs would spill more and
+// the FP32 kernels need no hint, so the compiler chooses.
 template <typename T, int EDDY, int CONV, int MODE>
 constexpr int kPatchMinWaves =
     (std::is_same<T, double>::value && MODE == kForward)                                        ? 6
-    : (std::is_same<T, double>::value && MODE == kVjp && EDDY == kNoEddy && CONV == kAdvective) ? 5
+    : (std::is_same<T, double>::value && MODE == kVjp && EDDY != kVreman && CONV == kAdvective) ? 5
                                                                                                 : 1;
 
 template <typename T, int EDDY, int CONV, int MODE, bool GATHER>
@@ -791,20 +792,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
     constexpr int kSP = std::is_same<T, double>::value ? kS + 8 : kS;
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
-    // The forwards and the FP64 advective VJP without eddy viscosity pad each
-    // row of the node arrays by 32 floats / 16 doubles, so that the fields of
-    // one node lie in different LDS bank pairs: with 256-entry rows the
-    // compiler pairs the reads of two fields of a vertex into one instruction
-    // whose two addresses share a bank pair.  Measured at 96^3 / 160^3: FP64
-    // forward 66.8 -> 63.9 us, with Smagorinsky 96-102 -> 91-92 us (once its
-    // eddy model lost its library calls), FP64 VJP 81.2 -> 78.9 us (held to
-    // five waves, see kPatchMinWaves), FP32 forward -2 %.  The FP32 VJPs
+    // The forwards and the FP64 VJPs pad each row of the node arrays by 32
+    // floats / 16 doubles, so that the fields of one node lie in different
+    // LDS bank pairs: with 256-entry rows the compiler pairs the reads of two
+    // fields of a vertex into one instruction whose two addresses share a
+    // bank pair.  Measured at 96^3 / 160^3: FP64 forward 66.8 -> 63.9 us, with
+    // Smagorinsky 96-102 -> 91-92 us (once its eddy model lost its library
+    // calls), FP64 advective VJP 81.2 -> 78.9 us (held to five waves, see
+    // kPatchMinWaves), FP64 VJPs with an eddy model -5 to -9 %, with the
+    // other convective forms -1 to -7 %, FP32 forward -2 %.  The FP32 VJPs
     // measured slower with it (instruction mix, registers) and keep 256-entry
-    // rows, as do the FP64 VJPs with an eddy model or a general convective
-    // form, which have not been measured padded.
+    // rows.
     constexpr bool kPadRows =
         MODE == kForward ||
-        (MODE == kVjp && std::is_same<T, double>::value && EDDY == kNoEddy && CONV == kAdvective);
+        (MODE == kVjp && std::is_same<T, double>::value);
     constexpr int kNR = kN + (kPadRows ? (std::is_same<T, double>::value ? 16 : 32) : 0);
     constexpr size_t kNodeBytes = 3 * kNR * sizeof(double) + kNF * kNR * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kSP * sizeof(T);
