@@ -792,20 +792,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kPatch
     constexpr int kN = kMaxPatchNodes, kS = 4 * kMaxPatchElems;
     constexpr int kSP = std::is_same<T, double>::value ? kS + 8 : kS;
     constexpr int kNF = FL::NA + FL::NB + FL::NC;
-    // The forwards and the FP64 VJPs pad each row of the node arrays by 32
-    // floats / 16 doubles, so that the fields of one node lie in different
+    // The forwards and the FP64 velocity and pressure VJPs pad each row of
+    // the node arrays by 32 floats / 16 doubles, so that the fields of one node lie in different
     // LDS bank pairs: with 256-entry rows the compiler pairs the reads of two
     // fields of a vertex into one instruction whose two addresses share a
     // bank pair.  Measured at 96^3 / 160^3: FP64 forward 66.8 -> 63.9 us, with
     // Smagorinsky 96-102 -> 91-92 us (once its eddy model lost its library
     // calls), FP64 advective VJP 81.2 -> 78.9 us (held to five waves, see
     // kPatchMinWaves), FP64 VJPs with an eddy model -5 to -9 %, with the
-    // other convective forms -1 to -7 %, FP32 forward -2 %.  The FP32 VJPs
-    // measured slower with it (instruction mix, registers) and keep 256-entry
-    // rows.
+    // other convective forms -1 to -7 %, FP64 pressure VJP -4 %, FP32
+    // forward -2 %.  The FP32 VJPs measured slower with it (instruction mix,
+    // registers) and keep 256-entry rows; the FP64 JVPs would lose a wave
+    // per SIMD (or spill) and keep them too.
     constexpr bool kPadRows =
         MODE == kForward ||
-        (MODE == kVjp && std::is_same<T, double>::value);
+        (std::is_same<T, double>::value && (MODE == kVjp || MODE == kVjpP));
     constexpr int kNR = kN + (kPadRows ? (std::is_same<T, double>::value ? 16 : 32) : 0);
     constexpr size_t kNodeBytes = 3 * kNR * sizeof(double) + kNF * kNR * sizeof(T);
     constexpr size_t kSlotBytes = FL::NOUT * kSP * sizeof(T);
